@@ -1,0 +1,174 @@
+/*
+ * sphfilt.h -- C-ABI of the double FFT filter for spherical grids on MI355X.
+ *
+ * The operation (arXiv:2305.01537, Sec. II.B "Filtering algorithms"):
+ *
+ *   Every evolved field X(x1, theta, phi) is filtered first along theta, then
+ *   along phi.
+ *   Theta-pass: theta is extended across the poles to a 2pi-periodic line by
+ *     pairing meridian phi with meridian phi + pi under the field's axis
+ *     parity sign (-1)^a (the extension equation), the line is transformed,
+ *     mode l is multiplied by f(|l|, l_max) and the result transformed back
+ *     and written to both meridians.
+ *   Phi-pass: every ring (x1, theta_j) is transformed along phi, mode m is
+ *     multiplied by f(|m|, m_max) and transformed back.
+ *   Cutoffs (the l_max / m_max equations):
+ *     l_max = max(floor, 2 (r/dr_min) L),
+ *     m_max = max(floor, 2 (r/dr_min) sin(theta_j) L), floor = 2 in the paper.
+ *   Filter kinds: exponential (eq. exp_filter), Gaussian (eq. gaussian_filter)
+ *     and the spectrally sharp low-pass mentioned beside them.
+ *
+ * Grid and layout, fixed by this library:
+ *   fields are FP64, contiguous, C order [n_fields][n_r][n_theta][n_phi]
+ *   (phi fastest); theta_j = (j + 1/2) pi / n_theta (cell centred, no point on
+ *   a pole), phi_k = 2 pi k / n_phi; n_phi must be even.  The extended half of
+ *   a theta line maps row n (n >= n_theta) to row 2 n_theta - 1 - n of
+ *   meridian k + n_phi/2.  sin(theta_j) is evaluated at the mirror-symmetric
+ *   colatitude (min(j, n_theta-1-j) + 1/2) pi / n_theta.
+ *
+ * The forward filter is F = Phi o Theta.  Each pass is a real symmetric
+ * linear operator, so the adjoint (transpose) is F^T = Theta o Phi.
+ *
+ * Errors: every entry point returns an int status (SPHFILT_OK or a negative
+ * SPHFILT_E* code); nothing is thrown across the ABI.  Arguments are
+ * validated on the host before any device call.  Device entry points only
+ * enqueue work on the given HIP stream and return; the caller synchronises.
+ *
+ * Supported sizes in this build: 2*n_theta and n_phi each in
+ * {32, 64, 128, 256}; other sizes return SPHFILT_EUNSUPPORTED.
+ */
+#ifndef SPHFILT_H
+#define SPHFILT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SPHFILT_OK            0
+#define SPHFILT_EINVAL       (-1)  /* bad argument (shape, pointer, parity, cutoff) */
+#define SPHFILT_ENOMEM       (-2)  /* host or device allocation failed            */
+#define SPHFILT_EDEVICE      (-3)  /* HIP runtime or kernel launch error          */
+#define SPHFILT_EUNSUPPORTED (-4)  /* valid for the method, not built here (size) */
+
+/* ---- filter kinds (Sec. II.B) ----------------------------------------- */
+#define SPHFILT_EXP   0   /* f = 1 for |l| <= c, exp(-(|l| - c)) above        (eq. exp_filter)      */
+#define SPHFILT_GAUSS 1   /* f = exp(log(0.9) (|l| / (c + 1))^2)               (eq. gaussian_filter) */
+#define SPHFILT_SHARP 2   /* f = 1 for |l| <= c, 0 above (sharp low-pass named beside eq. exp_filter) */
+
+typedef struct sphfilt_plan_s  *sphfilt_plan;   /* opaque; immutable after create */
+typedef struct sphfilt_batch_s *sphfilt_batch;  /* opaque; see sphfilt_batch_create */
+
+/*
+ * Cutoff parameters (Sec. II.B, l_max / m_max equations).
+ *   rho          [n_r] r_i / dr_min, each finite and > 0 (r is the physical
+ *                radius, e.g. after a fisheye map).  NULL => uniform
+ *                cell-centred grid rho_i = i + 1/2.
+ *   L            [n_fields] the cutoff scale cal-L, each finite and > 0
+ *                (the paper uses 3 for metric fields and 12 for matter).
+ *   kind         [n_fields] SPHFILT_EXP / GAUSS / SHARP, or NULL => all EXP.
+ *   floor_modes  finite, >= 0: the lowest cutoff; 2 in the paper.
+ * The arrays are read during the call only; the plan keeps its own copy.
+ */
+typedef struct {
+    const double *rho;
+    const double *L;
+    const int    *kind;
+    double        floor_modes;
+} sphfilt_cutoff;
+
+/*
+ * Work and traffic figures of one plan, computed on the host.
+ *   theta_shells_active  shells (field, r) whose theta mask is not all ones
+ *   theta_lines_*        extended theta lines (one per meridian pair)
+ *   phi_rings_*          phi rings
+ *   bytes_*              algorithmic HBM bytes of one call: 8 B read + 8 B
+ *                        written per point of every line a pass must touch.
+ *                        In place, identity lines are skipped; out of place,
+ *                        the first pass also copies its identity lines.
+ */
+typedef struct {
+    long long n_points;
+    long long theta_shells_total, theta_shells_active;
+    long long theta_lines_total, theta_lines_active;
+    long long phi_rings_total, phi_rings_active;
+    long long bytes_forward_inplace, bytes_forward_outofplace;
+    long long bytes_adjoint_inplace, bytes_adjoint_outofplace;
+} sphfilt_stats;
+
+/*
+ * Create a plan for n_fields fields on an n_r x n_theta x n_phi grid.
+ *   out     receives the plan handle (set to NULL on error).
+ *   parity  [n_fields] axis parity sign (-1)^a of each field, +1 or -1
+ *           (Sec. II.B, the extension equation).
+ *   cut     cutoff parameters, see sphfilt_cutoff.
+ * Builds the cutoff tables, the lists of non-identity lines and the twiddle
+ * tables on the host, then allocates and uploads them to the current HIP
+ * device.  The plan owns that device memory until sphfilt_plan_destroy and
+ * keeps no scratch, so one plan may be applied concurrently on several
+ * streams.
+ * Returns SPHFILT_EINVAL for n_* <= 0, odd n_phi, NULL pointers, parity not
+ * +-1, non-finite or non-positive rho / L, unknown kind, bad floor;
+ * SPHFILT_EUNSUPPORTED for sizes outside this build; SPHFILT_ENOMEM /
+ * SPHFILT_EDEVICE when allocation or upload fails.
+ */
+int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int n_fields,
+                        const int *parity, const sphfilt_cutoff *cut);
+
+/* Release the plan's device tables.  NULL is accepted.  Not stream-ordered:
+ * the caller makes sure no enqueued call still uses the plan. */
+int sphfilt_plan_destroy(sphfilt_plan plan);
+
+/*
+ * out = Phi(Theta(in)): the double FFT filter, theta first (Sec. II.B).
+ *   in, out  device pointers to n_fields*n_r*n_theta*n_phi doubles, layout
+ *            [f][r][theta][phi].  in == out (in place) is allowed and is the
+ *            fast path: lines whose mask is all ones are not touched.  Any
+ *            other overlap of the two ranges is SPHFILT_EINVAL.
+ *   stream   a hipStream_t (NULL = the null stream).
+ * Enqueues two kernels and returns; SPHFILT_EDEVICE if a launch fails.
+ */
+int sphfilt_apply(sphfilt_plan plan, const double *in, double *out, void *stream);
+
+/* out = Theta(Phi(in)) = F^T in: the transpose of sphfilt_apply (each pass is
+ * real symmetric).  Arguments and errors as for sphfilt_apply. */
+int sphfilt_apply_adjoint(sphfilt_plan plan, const double *in, double *out, void *stream);
+
+/* The theta-pass alone (Sec. II.B, theta FFT filter on extended lines).
+ * Arguments and errors as for sphfilt_apply. */
+int sphfilt_apply_theta(sphfilt_plan plan, const double *in, double *out, void *stream);
+
+/* The phi-pass alone (Sec. II.B, phi FFT filter on rings). */
+int sphfilt_apply_phi(sphfilt_plan plan, const double *in, double *out, void *stream);
+
+/* Work and traffic figures of a plan (host only, no device call). */
+int sphfilt_plan_stats(sphfilt_plan plan, sphfilt_stats *out);
+
+/* The same figures for a would-be plan, without creating one or touching a
+ * device; validates exactly like sphfilt_plan_create. */
+int sphfilt_workload_stats(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
+                           const sphfilt_cutoff *cut, sphfilt_stats *out);
+
+/*
+ * Launch shape of a plan's kernels (tuning; results do not depend on it).
+ *   theta_cols  meridian pairs per workgroup of the theta kernel: 8 or 16
+ *               (capped at n_phi/4).  0 keeps the current value.
+ *   phi_lines   ring pairs per workgroup of the phi kernel: 4, 8, 16, 32
+ *               or 64 (capped so a workgroup has at most 256 lanes).  0 keeps
+ *               the current value.
+ * Returns SPHFILT_EINVAL for other values.  Not thread-safe against
+ * concurrent apply calls on the same plan.
+ */
+int sphfilt_plan_set_schedule(sphfilt_plan plan, int theta_cols, int phi_lines);
+int sphfilt_plan_get_schedule(sphfilt_plan plan, int *theta_cols, int *phi_lines);
+
+/* Human-readable text of a status code (static storage). */
+const char *sphfilt_status_string(int status);
+
+/* Library version, "major.minor.patch" (static storage). */
+const char *sphfilt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHFILT_H */

@@ -1,0 +1,52 @@
+// sphfilt_internal.h -- types shared by the host plan and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sphfilt {
+
+// Item flags: low two bits are the filter kind (SPHFILT_EXP / GAUSS / SHARP).
+enum : int {
+    kKindMask = 3,
+    kFlagOddParity = 4,    // axis parity sign -1
+    kFlagIdentity = 8,     // mask is 1 for every mode of the line: copy only
+};
+
+// One shell (field f, radius i) of the theta-pass: every meridian pair of the
+// shell shares l_max.  shell = f * n_r + i.
+struct ThetaItem {
+    int32_t shell;
+    int32_t flags;
+    double c;              // l_max
+};
+
+// One ring pair (j, n_theta-1-j) of the phi-pass; both rings have the same
+// m_max because sin(theta) is evaluated on the mirror-symmetric colatitude.
+// ring = (f * n_r + i) * n_theta + j with j < n_theta / 2.
+struct PhiItem {
+    int32_t ring;
+    int32_t flags;
+    double c;              // m_max
+};
+
+struct Twiddle {
+    double re, im;         // exp(-2 pi i j / N)
+};
+
+// Launchers (kernels.hip).  All return hipSuccess or the launch error.
+// theta: n_items shells, each split in tiles of 2*cols meridian columns.
+hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
+                        const ThetaItem *items, int n_items, int n_theta, int n_phi,
+                        const Twiddle *tw, hipStream_t stream);
+// phi: n_items ring pairs, `lines` of them per workgroup.
+hipError_t launch_phi(int n_line, int lines, const double *in, double *out, const PhiItem *items,
+                      int n_items, int n_theta, const Twiddle *tw, hipStream_t stream);
+
+// Whether a (line length, launch shape) pair has a compiled kernel.
+bool theta_shape_ok(int n_line, int cols, int n_phi);
+bool phi_shape_ok(int n_line, int lines);
+int default_theta_cols(int n_phi);
+int default_phi_lines(int n_line);
+
+}  // namespace sphfilt

@@ -1,0 +1,180 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Acceptance (relative max-norm): ||Z_gpu - Z_oracle||_inf / ||Z_oracle||_inf <= 1e-12,
+for the forward filter, its adjoint and each pass alone, in place and out of
+place.  Bit-exact where the method is exact: lines whose mask is all ones are
+copied or left untouched, results do not depend on the launch shape, and
+in-place equals out-of-place.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_01537_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+CALLS = {
+    "forward": ("apply", oracle.forward),
+    "adjoint": ("apply_adjoint", oracle.adjoint),
+    "theta": ("apply_theta", oracle.theta_pass),
+    "phi": ("apply_phi", oracle.phi_pass),
+}
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def make_plan(shape, parity, L, rho=None, kind=None, floor=2.0):
+    from paper_2305_01537_amd.filter import Plan
+    F, R, T, P = shape
+    return Plan(R, T, P, F, parity=parity, L=L, rho=rho, kind=kind, floor_modes=floor)
+
+
+def gpu_call(torch, plan, call, x, inplace):
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    fn = getattr(plan, CALLS[call][0])
+    out = fn(xd, out=xd) if inplace else fn(xd)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def check_all(torch, x, parity, L, rho=None, kind=None, floor=2.0, calls=("forward", "adjoint", "theta", "phi")):
+    shape = x.shape
+    plan = make_plan(shape, parity, L, rho, kind, floor)
+    kind_o = 0 if kind is None else kind
+    for call in calls:
+        ref = CALLS[call][1](x, parity=parity, rho=rho, L=L, kind=kind_o, floor_modes=floor)
+        out_oop = gpu_call(torch, plan, call, x, inplace=False)
+        out_ip = gpu_call(torch, plan, call, x, inplace=True)
+        assert rel(out_oop, ref) <= TOL, (call, "out-of-place", rel(out_oop, ref))
+        assert np.array_equal(out_ip, out_oop), (call, "in-place differs from out-of-place")
+    plan.close()
+
+
+def test_small_workload(torch_gpu):
+    w = synth.workload("small")
+    print(f"[gpu] small {w.shape}", flush=True)
+    check_all(torch_gpu, w.x, w.parity, w.L, w.rho)
+
+
+@pytest.mark.parametrize("L", [3.0, 0.2, 12.0])
+def test_grmhd_slice(torch_gpu, L):
+    w = synth.workload("grmhd", shape=(6, 20, 64, 128))
+    print(f"[gpu] grmhd slice {w.shape} L={L}", flush=True)
+    check_all(torch_gpu, w.x, w.parity, np.full(6, L), w.rho)
+
+
+@pytest.mark.parametrize("n_theta,n_phi", [(16, 32), (16, 64), (32, 64), (32, 32), (64, 128),
+                                           (64, 256), (128, 256), (128, 64), (16, 256), (128, 32)])
+def test_every_supported_size(torch_gpu, n_theta, n_phi):
+    rng = np.random.default_rng(n_theta * 1000 + n_phi)
+    shape = (3, 5, n_theta, n_phi)
+    x = rng.standard_normal(shape)
+    parity = np.array([1, -1, -1], dtype=np.int32)
+    print(f"[gpu] size {shape}", flush=True)
+    # small L: both passes active on most lines; mixed kinds per field
+    check_all(torch_gpu, x, parity, np.array([0.3, 1.1, 0.45]), kind=np.array([0, 1, 2], dtype=np.int32))
+
+
+def test_fisheye_radius_and_floor(torch_gpu):
+    rng = np.random.default_rng(7)
+    shape = (4, 9, 32, 64)
+    x = rng.standard_normal(shape)
+    # exponential fisheye: r grows geometrically while dr_min is fixed
+    rho = 0.5 * np.exp(0.35 * np.arange(9))
+    parity = np.array([1, -1, 1, -1], dtype=np.int32)
+    print(f"[gpu] fisheye {shape}", flush=True)
+    check_all(torch_gpu, x, parity, np.array([3.0, 3.0, 12.0, 0.7]), rho=rho,
+              kind=np.array([0, 2, 1, 0], dtype=np.int32), floor=3.5)
+
+
+def test_identity_cutoff_is_bitwise(torch_gpu):
+    # every cutoff above the Nyquist mode: the filter is exactly the identity
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((2, 6, 32, 64))
+    plan = make_plan(x.shape, np.array([1, -1]), np.array([500.0, 500.0]))
+    st = plan.stats()
+    assert st["theta_shells_active"] == 0 and st["phi_rings_active"] == 0
+    for call in CALLS:
+        assert np.array_equal(gpu_call(torch_gpu, plan, call, x, inplace=False), x)
+        assert np.array_equal(gpu_call(torch_gpu, plan, call, x, inplace=True), x)
+
+
+def test_schedules_are_bitwise_equal_and_deterministic(torch_gpu):
+    torch = torch_gpu
+    w = synth.workload("grmhd", shape=(5, 12, 64, 128))
+    plan = make_plan(w.shape, w.parity, np.full(5, 0.9), w.rho)
+    xd = torch.from_numpy(w.x).cuda()
+    ref = plan.apply(xd).cpu().numpy()
+    assert np.array_equal(plan.apply(xd).cpu().numpy(), ref)
+    for tc in (8, 16):
+        for pl in (4, 8, 16, 32):
+            plan.set_schedule(tc, pl)
+            assert plan.get_schedule() == (tc, pl)
+            got = plan.apply(xd)
+            got_a = plan.apply_adjoint(xd)
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), ref), (tc, pl)
+            if tc == 8 and pl == 4:
+                ref_a = got_a.cpu().numpy()
+            else:
+                assert np.array_equal(got_a.cpu().numpy(), ref_a), (tc, pl)
+
+
+def test_partial_overlap_rejected(torch_gpu):
+    from paper_2305_01537_amd.filter import SphfiltError
+    torch = torch_gpu
+    plan = make_plan((1, 4, 16, 32), 1, 3.0)
+    buf = torch.zeros(2 * 4 * 16 * 32, dtype=torch.float64, device="cuda")
+    a = buf[: 4 * 16 * 32].view(1, 4, 16, 32)
+    b = buf[32: 32 + 4 * 16 * 32].view(1, 4, 16, 32)
+    with pytest.raises(SphfiltError):
+        plan.apply(a, out=b)
+
+
+def test_empty_and_tiny_grids(torch_gpu):
+    # a single shell and a single field; the phi item list is shorter than one workgroup
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((1, 1, 16, 32))
+    check_all(torch_gpu, x, np.array([-1]), np.array([0.6]))
+    check_all(torch_gpu, x, np.array([1]), np.array([0.6]), kind=np.array([1], dtype=np.int32))
+
+
+def test_grmhd_full_forward_adjoint(torch_gpu):
+    w = synth.workload("grmhd")
+    print(f"[gpu] grmhd full {w.shape}", flush=True)
+    check_all(torch_gpu, w.x, w.parity, w.L, w.rho, calls=("forward", "adjoint"))
+
+
+def test_share_full_size_sampled_shells(torch_gpu):
+    """The 24 x 256 x 128 x 256 production share, in the launch shape the benchmark
+    times (in place, default schedule); the oracle checks sampled whole shells."""
+    torch = torch_gpu
+    w = synth.workload("share")
+    print(f"[gpu] share {w.shape}", flush=True)
+    for L in (3.0, 0.2):
+        plan = make_plan(w.shape, w.parity, np.full(24, L), w.rho)
+        xd = torch.from_numpy(w.x).cuda()
+        plan.apply(xd, out=xd)
+        ya = plan.apply_adjoint(torch.from_numpy(w.x).cuda())
+        torch.cuda.synchronize()
+        fwd, adj = xd.cpu().numpy(), ya.cpu().numpy()
+        del xd, ya
+        rng = np.random.default_rng(33)
+        picks = [(0, 0), (23, 255), (5, 20), (11, 21)] + [tuple(v) for v in zip(rng.integers(0, 24, 4), rng.integers(0, 256, 4))]
+        for f, i in picks:
+            sub = w.x[f:f + 1, i:i + 1]
+            kw = dict(parity=w.parity[f:f + 1], rho=w.rho[i:i + 1], L=L)
+            assert rel(fwd[f:f + 1, i:i + 1], oracle.forward(sub, **kw)) <= TOL, (L, f, i)
+            assert rel(adj[f:f + 1, i:i + 1], oracle.adjoint(sub, **kw)) <= TOL, (L, f, i)
+        plan.close()
