@@ -230,14 +230,24 @@ __global__ __launch_bounds__(LINES * Split<N>::N2) void phi_kernel(
         constexpr int n1 = decltype(nn)::value;
         v[n1] = valid ? cplx{in[a + N2 * n1 + t], in[b + N2 * n1 + t]} : cplx{0.0, 0.0};
     });
+    // Identity lines that share a workgroup with filtered ones run through the
+    // transform too (the barriers are workgroup-wide) but their result is
+    // dropped: they are copied exactly from `in` instead.  Such workgroups
+    // only occur out of place, where `in` is not written.
     if (any_active)
         filter_line<N1, N2>(v, t, it.flags & kKindMask, active ? it.c : INFINITY,
                             lds + p * line_lds<N1, N2>(), tw);
-    if (valid) {
+    if (valid && (active || !any_active)) {
         static_for<0, N1>([&](auto nn) {
             constexpr int n1 = decltype(nn)::value;
             out[a + N2 * n1 + t] = v[n1].re;
             out[b + N2 * n1 + t] = v[n1].im;
+        });
+    } else if (valid && in != out) {
+        static_for<0, N1>([&](auto nn) {
+            constexpr int n1 = decltype(nn)::value;
+            out[a + N2 * n1 + t] = in[a + N2 * n1 + t];
+            out[b + N2 * n1 + t] = in[b + N2 * n1 + t];
         });
     }
 }
