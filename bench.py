@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--L", type=float, default=3.0, help="cutoff scale cal-L of every field")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="after the timed loops, run plain copies of the workload buffer "
+                         "(reference for the HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -66,25 +69,35 @@ def time_loop(torch, fn, bufs, steps, warmup, stream):
 
 
 def cpu_baseline(w, L, budget_s):
-    """The oracle as it stands, timed on whole shells of the same workload."""
+    """The oracle as it stands, timed on whole shells of the same workload:
+    one shell first to size the sample, then that many shells (field-major)."""
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    # one shell first to size the sample
-    f = 0
+    F, R = w.shape[0], w.shape[1]
     t = time.perf_counter()
-    oracle.forward(w.x[f:f + 1, 0:1], parity=w.parity[f:f + 1], rho=w.rho[0:1], L=L)
+    oracle.forward(w.x[0:1, 0:1], parity=w.parity[0:1], rho=w.rho[0:1], L=L)
     one = time.perf_counter() - t
-    n_sh = int(max(1, min(w.shape[1], budget_s / max(one, 1e-6))))
-    n_sh = max(n_sh, 1)
-    sub = np.ascontiguousarray(w.x[f:f + 1, :n_sh])
+    n_sh = int(max(1, min(F * R, budget_s / max(one, 1e-6))))
+    n_f = max(1, n_sh // R) if n_sh >= R else 1
+    n_r = R if n_sh >= R else n_sh
+    sub = np.ascontiguousarray(w.x[:n_f, :n_r])
     t = time.perf_counter()
-    oracle.forward(sub, parity=w.parity[f:f + 1], rho=w.rho[:n_sh], L=L)
+    oracle.forward(sub, parity=w.parity[:n_f], rho=w.rho[:n_r], L=L)
     dt = time.perf_counter() - t
-    pts = sub.size
-    return {"value": pts / dt, "unit": "field-points/s", "cores": threads, "kind": "oracle",
-            "sample": f"field 0, shells 0..{n_sh - 1} of the share workload "
-                      f"({n_sh} x 128 x 256 points, cal-L={L}), forward filter, {dt:.1f} s"}
+    return {"value": sub.size / dt, "unit": "field-points/s", "cores": threads, "kind": "oracle",
+            "sample": f"fields 0..{n_f - 1} x shells 0..{n_r - 1} of the share workload "
+                      f"({sub.size} points, cal-L={L}), forward filter (theta then phi, "
+                      f"direct DFTs), {dt:.1f} s"}
+
+
+def calibrate_copy(torch, x, reps=3):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"copy_bytes_each": 2 * x.numel() * 8, "reps": reps}
 
 
 def main():
@@ -173,6 +186,8 @@ def main():
         }
         log(f"dense: {extra['dense']}")
         dplan.close()
+    if args.calibrate:
+        extra["calibration"] = calibrate_copy(torch, x0)
     del bufs, x0
     torch.cuda.empty_cache()
 

@@ -27,18 +27,82 @@ namespace sphfilt {
 // ln(0.9), the Gaussian filter's constant (eq. gaussian_filter).
 constexpr double kLog09 = -0.10536051565782630123;
 
-__device__ __forceinline__ double mask_value(int kind, int qhat, double c)
+// Field data is streamed exactly once per pass: non-temporal loads and stores
+// keep it from displacing the small tables in the caches.
+#ifndef SPHFILT_NT
+#define SPHFILT_NT 1
+#endif
+// Minimum waves per SIMD requested from the register allocator (0: compiler's
+// choice).  Bounds the VGPR count of the large-N kernels.
+#ifndef SPHFILT_WAVES
+#define SPHFILT_WAVES 0
+#endif
+#if SPHFILT_WAVES > 0
+#define SPHFILT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SPHFILT_WAVES)))
+#else
+#define SPHFILT_OCCUPANCY
+#endif
+
+__device__ __forceinline__ double ld_stream(const double *p)
 {
-    const double q = (double)qhat;
-    switch (kind) {
-    case 0:  // exponential: 1 up to the cutoff, exp(-(|q| - c)) above
-        return q <= c ? 1.0 : exp(-(q - c));
-    case 1: {  // Gaussian: exp(log(0.9) (|q| / (c + 1))^2)
-        const double u = q / (c + 1.0);
-        return exp(kLog09 * u * u);
-    }
-    default:  // sharp low-pass
-        return q <= c ? 1.0 : 0.0;
+#if SPHFILT_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+__device__ __forceinline__ void st_stream(double *p, double v)
+{
+#if SPHFILT_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// Mask of one line, with the inverse transform's 1/N folded in.  v holds
+// X[q] at q = t + N2 r + N1 k2 in v[r N2 + k2].
+//   exponential (eq. exp_filter): f = 1 for |q| <= c, else exp(-(|q| - c)).
+//     With m = floor(c), |q| <= c is |q| <= m, and above the cutoff
+//     exp(c - |q|) = exp(c - m - 1) * e^{-(|q| - m - 1)}: one exp per lane and
+//     a table of e^{-k}, instead of one exp per mode.
+//   sharp: the same with the factor above the cutoff set to 0.
+//   Gaussian (eq. gaussian_filter): f = exp(log(0.9) (|q| / (c + 1))^2).
+template <int N1, int N2>
+__device__ __forceinline__ void apply_mask(cplx (&v)[N1], int t, int kind, double c,
+                                           const double *etab)
+{
+    constexpr int N = N1 * N2;
+    constexpr int R = N1 / N2;
+    constexpr double inv_n = 1.0 / N;
+    if (kind == 1) {
+        const double inv = 1.0 / (c + 1.0);
+        static_for<0, R>([&](auto rr) {
+            constexpr int r = decltype(rr)::value;
+            static_for<0, N2>([&](auto kk) {
+                constexpr int k2 = decltype(kk)::value;
+                const int q = t + N2 * r + N1 * k2;
+                const double u = (double)(q <= N / 2 ? q : N - q) * inv;
+                const double f = exp(kLog09 * u * u) * inv_n;
+                v[r * N2 + k2].re *= f;
+                v[r * N2 + k2].im *= f;
+            });
+        });
+    } else {
+        const int m = c >= (double)N ? N : (int)floor(c);
+        const double g = (kind == 0 ? exp((c - (double)m) - 1.0) : 0.0) * inv_n;
+        static_for<0, R>([&](auto rr) {
+            constexpr int r = decltype(rr)::value;
+            static_for<0, N2>([&](auto kk) {
+                constexpr int k2 = decltype(kk)::value;
+                const int q = t + N2 * r + N1 * k2;
+                const int qhat = q <= N / 2 ? q : N - q;
+                const double f = qhat <= m ? inv_n : g * etab[qhat > m ? qhat - m - 1 : 0];
+                v[r * N2 + k2].re *= f;
+                v[r * N2 + k2].im *= f;
+            });
+        });
     }
 }
 
@@ -97,56 +161,73 @@ __device__ __forceinline__ void transpose_bwd(cplx (&v)[N1], int t, double *L)
     });
 }
 
+// v[OFF + k] *= w^k (or conj(w)^k with CONJ) for k in [1, K), where
+// w^j = tw[j * s].  Powers are formed as w^(4a + b) = w^(4a) * w^b from the
+// table entries w^1..w^3 and w^4, w^8, ...: a handful of loads and at most
+// one rounding per twiddle.  Needs (K - 1) * s < N.
+template <int K, bool CONJ, int OFF, int NV>
+__device__ __forceinline__ void twiddle_powers(cplx (&v)[NV], const Twiddle *__restrict__ tw, int s)
+{
+    cplx lo[4], hi[(K + 3) / 4];
+    lo[0] = cplx{1.0, 0.0};
+    hi[0] = cplx{1.0, 0.0};
+    static_for<1, (K < 4 ? K : 4)>([&](auto bb) {
+        constexpr int b = decltype(bb)::value;
+        const Twiddle w = tw[b * s];
+        lo[b] = cplx{w.re, w.im};
+    });
+    static_for<1, (K + 3) / 4>([&](auto aa) {
+        constexpr int a = decltype(aa)::value;
+        const Twiddle w = tw[4 * a * s];
+        hi[a] = cplx{w.re, w.im};
+    });
+    static_for<1, K>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        constexpr int a = k / 4, b = k % 4;
+        cplx w;
+        if constexpr (a == 0) w = lo[b];
+        else if constexpr (b == 0) w = hi[a];
+        else w = cmul(hi[a], lo[b]);
+        v[OFF + k] = CONJ ? cmulc(v[OFF + k], w) : cmul(v[OFF + k], w);
+    });
+}
+
 // Filter one complex line of length N = N1 * N2 held by N2 lanes (lane t
 // holds x[N2 n1 + t] in v[n1]); on return v holds the filtered values at the
 // same positions.  Every lane of the workgroup calls this together.
+// etab: e^{-k}, k <= N/2, in LDS, written before the first barrier here.
 template <int N1, int N2>
 __device__ __forceinline__ void filter_line(cplx (&v)[N1], int t, int kind, double c, double *L,
-                                            const Twiddle *__restrict__ tw)
+                                            const Twiddle *__restrict__ tw, const double *etab)
 {
-    constexpr int N = N1 * N2;
     constexpr int R = N1 / N2;
     static_assert(N1 % N2 == 0, "lane count must divide the register count");
 
     // forward: N1-point DFTs over n1, twiddle W_N^{t k1}
     dft_reg<N1, false>(v);
-    static_for<1, N1>([&](auto kk) {
-        constexpr int k1 = decltype(kk)::value;
-        const Twiddle w = tw[t * k1];
-        v[k1] = cmul(v[k1], cplx{w.re, w.im});
-    });
+    twiddle_powers<N1, false, 0>(v, tw, t);
     transpose_fwd<N1, N2>(v, t, L);
     // N2-point DFTs over n2: v[r N2 + k2] = X[k1 + N1 k2], k1 = t + N2 r
     static_for<0, R>([&](auto rr) { dft_reg<N2, false, decltype(rr)::value * N2>(v); });
 
-    // mask, with the inverse transform's 1/N folded in
-    static_for<0, R>([&](auto rr) {
-        constexpr int r = decltype(rr)::value;
-        static_for<0, N2>([&](auto kk) {
-            constexpr int k2 = decltype(kk)::value;
-            const int q = t + N2 * r + N1 * k2;
-            const int qhat = q <= N / 2 ? q : N - q;
-            const double f = mask_value(kind, qhat, c) * (1.0 / N);
-            v[r * N2 + k2].re *= f;
-            v[r * N2 + k2].im *= f;
-        });
-    });
+    apply_mask<N1, N2>(v, t, kind, c, etab);
 
-    // inverse: N2-point inverse DFTs, conjugate twiddles, transpose back,
-    // N1-point inverse DFTs
-    static_for<0, R>([&](auto rr) { dft_reg<N2, true, decltype(rr)::value * N2>(v); });
+    // inverse: N2-point inverse DFTs, conjugate twiddles W_N^{-n2 k1},
+    // transpose back, N1-point inverse DFTs
     static_for<0, R>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
-        static_for<0, N2>([&](auto nn) {
-            constexpr int n2 = decltype(nn)::value;
-            if constexpr (n2 > 0) {
-                const Twiddle w = tw[n2 * (t + N2 * r)];
-                v[r * N2 + n2] = cmulc(v[r * N2 + n2], cplx{w.re, w.im});
-            }
-        });
+        dft_reg<N2, true, r * N2>(v);
+        twiddle_powers<N2, true, r * N2>(v, tw, t + N2 * r);
     });
     transpose_bwd<N1, N2>(v, t, L);
     dft_reg<N1, true>(v);
+}
+
+// Copy e^{-k}, k in [0, N/2], into the workgroup's LDS table.
+template <int N>
+__device__ __forceinline__ void stage_exp_table(double *etab, const double *__restrict__ eneg)
+{
+    for (int i = threadIdx.x; i <= N / 2; i += blockDim.x) etab[i] = eneg[i];
 }
 
 template <int N> struct Split;
@@ -161,45 +242,52 @@ template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
 // (real part) and ki = k0 + C + p (imaginary part).
 // ---------------------------------------------------------------------------
 template <int N, int C>
-__global__ __launch_bounds__(C * Split<N>::N2) void theta_kernel(
+__global__ __launch_bounds__(C * Split<N>::N2) SPHFILT_OCCUPANCY void theta_kernel(
     const double *in, double *out, const ThetaItem *__restrict__ items, int tiles_per_shell,
-    int n_theta, int n_phi, const Twiddle *__restrict__ tw)
+    int n_theta, int n_phi, const Twiddle *__restrict__ tw, const double *__restrict__ eneg)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
     __shared__ double lds[C * line_lds<N1, N2>()];
+    __shared__ double etab[N / 2 + 1];
     const int p = threadIdx.x % C, t = threadIdx.x / C;
     const int tile = blockIdx.x % tiles_per_shell;
     const ThetaItem it = items[blockIdx.x / tiles_per_shell];
+    const bool filtered = !(it.flags & kFlagIdentity);
+    if (filtered) stage_exp_table<N>(etab, eneg);
     const size_t base = (size_t)it.shell * (size_t)(n_theta * n_phi);
-    const double *src = in + base;
-    double *dst = out + base;
     const int half = n_phi / 2;
     const int kr = tile * 2 * C + p, ki = kr + C;
     const double s = (it.flags & kFlagOddParity) ? -1.0 : 1.0;
+    // Row n1 of the lane block starts at a workgroup-uniform row; the lane adds
+    // a small non-negative row offset and its column.  Rows N2 n1 + t of the
+    // first half; rows n_theta - N2 (n1 - N1/2 + 1) + (N2 - 1 - t) of the
+    // mirrored half, i.e. row 2 n_theta - 1 - (N2 n1 + t).
+    const int off_n = t * n_phi;
+    const int off_s = (N2 - 1 - t) * n_phi + half;
 
     cplx v[N1];
     static_for<0, N1>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
-        const int n = N2 * n1 + t;
         if constexpr (n1 < N1 / 2) {
-            v[n1] = cplx{src[n * n_phi + kr], src[n * n_phi + ki]};
+            const double *row = in + base + (size_t)(N2 * n1) * n_phi;
+            v[n1] = cplx{ld_stream(row + off_n + kr), ld_stream(row + off_n + ki)};
         } else {
-            const int row = N - 1 - n;
-            v[n1] = cplx{s * src[row * n_phi + kr + half], s * src[row * n_phi + ki + half]};
+            const double *row = in + base + (size_t)(N - N2 * (n1 + 1)) * n_phi;
+            v[n1] = cplx{s * ld_stream(row + off_s + kr), s * ld_stream(row + off_s + ki)};
         }
     });
-    if (!(it.flags & kFlagIdentity))
-        filter_line<N1, N2>(v, t, it.flags & kKindMask, it.c, lds + p * line_lds<N1, N2>(), tw);
+    if (filtered)
+        filter_line<N1, N2>(v, t, it.flags & kKindMask, it.c, lds + p * line_lds<N1, N2>(), tw, etab);
     static_for<0, N1>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
-        const int n = N2 * n1 + t;
         if constexpr (n1 < N1 / 2) {
-            dst[n * n_phi + kr] = v[n1].re;
-            dst[n * n_phi + ki] = v[n1].im;
+            double *row = out + base + (size_t)(N2 * n1) * n_phi;
+            st_stream(row + off_n + kr, v[n1].re);
+            st_stream(row + off_n + ki, v[n1].im);
         } else {
-            const int row = N - 1 - n;
-            dst[row * n_phi + kr + half] = s * v[n1].re;
-            dst[row * n_phi + ki + half] = s * v[n1].im;
+            double *row = out + base + (size_t)(N - N2 * (n1 + 1)) * n_phi;
+            st_stream(row + off_s + kr, s * v[n1].re);
+            st_stream(row + off_s + ki, s * v[n1].im);
         }
     });
 }
@@ -208,12 +296,13 @@ __global__ __launch_bounds__(C * Split<N>::N2) void theta_kernel(
 // phi-pass: one workgroup = LINES ring pairs; lane (p, t), t fastest.
 // ---------------------------------------------------------------------------
 template <int N, int LINES>
-__global__ __launch_bounds__(LINES * Split<N>::N2) void phi_kernel(
+__global__ __launch_bounds__(LINES * Split<N>::N2) SPHFILT_OCCUPANCY void phi_kernel(
     const double *in, double *out, const PhiItem *__restrict__ items, int n_items, int n_theta,
-    const Twiddle *__restrict__ tw)
+    const Twiddle *__restrict__ tw, const double *__restrict__ eneg)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
     __shared__ double lds[LINES * line_lds<N1, N2>()];
+    __shared__ double etab[N / 2 + 1];
     const int t = threadIdx.x % N2, p = threadIdx.x / N2;
     const int idx = blockIdx.x * LINES + p;
     const bool valid = idx < n_items;
@@ -221,6 +310,7 @@ __global__ __launch_bounds__(LINES * Split<N>::N2) void phi_kernel(
     if (valid) it = items[idx];
     const bool active = valid && !(it.flags & kFlagIdentity);
     const int any_active = __syncthreads_or(active);
+    if (any_active) stage_exp_table<N>(etab, eneg);
 
     const int j = it.ring % n_theta;
     const size_t a = (size_t)it.ring * N;
@@ -228,7 +318,8 @@ __global__ __launch_bounds__(LINES * Split<N>::N2) void phi_kernel(
     cplx v[N1];
     static_for<0, N1>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
-        v[n1] = valid ? cplx{in[a + N2 * n1 + t], in[b + N2 * n1 + t]} : cplx{0.0, 0.0};
+        v[n1] = valid ? cplx{ld_stream(in + a + N2 * n1 + t), ld_stream(in + b + N2 * n1 + t)}
+                      : cplx{0.0, 0.0};
     });
     // Identity lines that share a workgroup with filtered ones run through the
     // transform too (the barriers are workgroup-wide) but their result is
@@ -236,18 +327,18 @@ __global__ __launch_bounds__(LINES * Split<N>::N2) void phi_kernel(
     // only occur out of place, where `in` is not written.
     if (any_active)
         filter_line<N1, N2>(v, t, it.flags & kKindMask, active ? it.c : INFINITY,
-                            lds + p * line_lds<N1, N2>(), tw);
+                            lds + p * line_lds<N1, N2>(), tw, etab);
     if (valid && (active || !any_active)) {
         static_for<0, N1>([&](auto nn) {
             constexpr int n1 = decltype(nn)::value;
-            out[a + N2 * n1 + t] = v[n1].re;
-            out[b + N2 * n1 + t] = v[n1].im;
+            st_stream(out + a + N2 * n1 + t, v[n1].re);
+            st_stream(out + b + N2 * n1 + t, v[n1].im);
         });
     } else if (valid && in != out) {
         static_for<0, N1>([&](auto nn) {
             constexpr int n1 = decltype(nn)::value;
-            out[a + N2 * n1 + t] = in[a + N2 * n1 + t];
-            out[b + N2 * n1 + t] = in[b + N2 * n1 + t];
+            st_stream(out + a + N2 * n1 + t, ld_stream(in + a + N2 * n1 + t));
+            st_stream(out + b + N2 * n1 + t, ld_stream(in + b + N2 * n1 + t));
         });
     }
 }
@@ -292,24 +383,25 @@ bool phi_shape_ok(int n_line, int lines)
 
 template <int N, int C>
 static hipError_t theta_go(const double *in, double *out, const ThetaItem *items, int n_items,
-                           int n_theta, int n_phi, const Twiddle *tw, hipStream_t s)
+                           int n_theta, int n_phi, const Twiddle *tw, const double *eneg,
+                           hipStream_t s)
 {
     const int tiles = (n_phi / 2) / (2 * C);
     const dim3 grid((unsigned)(n_items * tiles)), block(C * Split<N>::N2);
-    theta_kernel<N, C><<<grid, block, 0, s>>>(in, out, items, tiles, n_theta, n_phi, tw);
+    theta_kernel<N, C><<<grid, block, 0, s>>>(in, out, items, tiles, n_theta, n_phi, tw, eneg);
     return hipGetLastError();
 }
 
 hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
                         const ThetaItem *items, int n_items, int n_theta, int n_phi,
-                        const Twiddle *tw, hipStream_t s)
+                        const Twiddle *tw, const double *eneg, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     if (!theta_shape_ok(n_line, cols, n_phi) || n_line != 2 * n_theta) return hipErrorInvalidValue;
 #define SPHFILT_THETA_CASE(NN)                                                                  \
     case NN:                                                                                    \
-        return cols == 16 ? theta_go<NN, 16>(in, out, items, n_items, n_theta, n_phi, tw, s)  \
-                          : theta_go<NN, 8>(in, out, items, n_items, n_theta, n_phi, tw, s);
+        return cols == 16 ? theta_go<NN, 16>(in, out, items, n_items, n_theta, n_phi, tw, eneg, s)  \
+                          : theta_go<NN, 8>(in, out, items, n_items, n_theta, n_phi, tw, eneg, s);
     switch (n_line) {
         SPHFILT_THETA_CASE(32)
         SPHFILT_THETA_CASE(64)
@@ -322,41 +414,43 @@ hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
 
 template <int N, int LINES>
 static hipError_t phi_go(const double *in, double *out, const PhiItem *items, int n_items,
-                         int n_theta, const Twiddle *tw, hipStream_t s)
+                         int n_theta, const Twiddle *tw, const double *eneg, hipStream_t s)
 {
     if constexpr (LINES * Split<N>::N2 > 256 || LINES * Split<N>::N2 < 16) {
         return hipErrorInvalidValue;
     } else {
         const dim3 grid((unsigned)((n_items + LINES - 1) / LINES)), block(LINES * Split<N>::N2);
-        phi_kernel<N, LINES><<<grid, block, 0, s>>>(in, out, items, n_items, n_theta, tw);
+        phi_kernel<N, LINES><<<grid, block, 0, s>>>(in, out, items, n_items, n_theta, tw, eneg);
         return hipGetLastError();
     }
 }
 
 template <int N>
 static hipError_t phi_lines(int lines, const double *in, double *out, const PhiItem *items,
-                            int n_items, int n_theta, const Twiddle *tw, hipStream_t s)
+                            int n_items, int n_theta, const Twiddle *tw, const double *eneg,
+                            hipStream_t s)
 {
     switch (lines) {
-    case 4: return phi_go<N, 4>(in, out, items, n_items, n_theta, tw, s);
-    case 8: return phi_go<N, 8>(in, out, items, n_items, n_theta, tw, s);
-    case 16: return phi_go<N, 16>(in, out, items, n_items, n_theta, tw, s);
-    case 32: return phi_go<N, 32>(in, out, items, n_items, n_theta, tw, s);
-    case 64: return phi_go<N, 64>(in, out, items, n_items, n_theta, tw, s);
+    case 4: return phi_go<N, 4>(in, out, items, n_items, n_theta, tw, eneg, s);
+    case 8: return phi_go<N, 8>(in, out, items, n_items, n_theta, tw, eneg, s);
+    case 16: return phi_go<N, 16>(in, out, items, n_items, n_theta, tw, eneg, s);
+    case 32: return phi_go<N, 32>(in, out, items, n_items, n_theta, tw, eneg, s);
+    case 64: return phi_go<N, 64>(in, out, items, n_items, n_theta, tw, eneg, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_phi(int n_line, int lines, const double *in, double *out, const PhiItem *items,
-                      int n_items, int n_theta, const Twiddle *tw, hipStream_t s)
+                      int n_items, int n_theta, const Twiddle *tw, const double *eneg,
+                      hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     if (!phi_shape_ok(n_line, lines)) return hipErrorInvalidValue;
     switch (n_line) {
-    case 32: return phi_lines<32>(lines, in, out, items, n_items, n_theta, tw, s);
-    case 64: return phi_lines<64>(lines, in, out, items, n_items, n_theta, tw, s);
-    case 128: return phi_lines<128>(lines, in, out, items, n_items, n_theta, tw, s);
-    case 256: return phi_lines<256>(lines, in, out, items, n_items, n_theta, tw, s);
+    case 32: return phi_lines<32>(lines, in, out, items, n_items, n_theta, tw, eneg, s);
+    case 64: return phi_lines<64>(lines, in, out, items, n_items, n_theta, tw, eneg, s);
+    case 128: return phi_lines<128>(lines, in, out, items, n_items, n_theta, tw, eneg, s);
+    case 256: return phi_lines<256>(lines, in, out, items, n_items, n_theta, tw, eneg, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -33,6 +33,7 @@ struct DeviceTables {
     PhiItem *phi = nullptr;
     Twiddle *tw_theta = nullptr;
     Twiddle *tw_phi = nullptr;
+    double *eneg = nullptr;
 };
 
 struct HostTables {
@@ -84,6 +85,14 @@ std::vector<Twiddle> twiddles(int N)
         t[(size_t)j] = Twiddle{c, -s};
     }
     return t;
+}
+
+// e^{-k}, k in [0, kExpTable): the exponential mask above its cutoff.
+std::vector<double> exp_table()
+{
+    std::vector<double> e((size_t)kExpTable);
+    for (int k = 0; k < kExpTable; ++k) e[(size_t)k] = std::exp(-(double)k);
+    return e;
 }
 
 int validate(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
@@ -179,6 +188,7 @@ void free_device(DeviceTables *d)
     if (d->phi) (void)hipFree(d->phi);
     if (d->tw_theta) (void)hipFree(d->tw_theta);
     if (d->tw_phi) (void)hipFree(d->tw_phi);
+    if (d->eneg) (void)hipFree(d->eneg);
     *d = DeviceTables{};
 }
 
@@ -218,10 +228,11 @@ int run_pass(sphfilt_plan p, Pass which, const double *in, double *out, bool all
     if (which == Pass::Theta) {
         const int n = all_items ? (int)p->host.theta.size() : p->host.theta_active;
         e = launch_theta(2 * p->n_theta, p->theta_cols, in, out, p->dev.theta, n, p->n_theta,
-                         p->n_phi, p->dev.tw_theta, s);
+                         p->n_phi, p->dev.tw_theta, p->dev.eneg, s);
     } else {
         const int n = all_items ? (int)p->host.phi.size() : p->host.phi_active;
-        e = launch_phi(p->n_phi, p->phi_lines, in, out, p->dev.phi, n, p->n_theta, p->dev.tw_phi, s);
+        e = launch_phi(p->n_phi, p->phi_lines, in, out, p->dev.phi, n, p->n_theta, p->dev.tw_phi,
+                       p->dev.eneg, s);
     }
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
@@ -303,6 +314,7 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
         if (!rc) rc = upload(&p->dev.phi, p->host.phi);
         if (!rc) rc = upload(&p->dev.tw_theta, twiddles(2 * n_theta));
         if (!rc) rc = upload(&p->dev.tw_phi, twiddles(n_phi));
+        if (!rc) rc = upload(&p->dev.eneg, exp_table());
     } catch (const std::bad_alloc &) {
         rc = SPHFILT_ENOMEM;
     }

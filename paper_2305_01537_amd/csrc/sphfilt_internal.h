@@ -30,18 +30,23 @@ struct PhiItem {
     double c;              // m_max
 };
 
+// Length of the e^{-k} table: covers k <= N/2 for every supported N.
+constexpr int kExpTable = 512;
+
 struct Twiddle {
     double re, im;         // exp(-2 pi i j / N)
 };
 
 // Launchers (kernels.hip).  All return hipSuccess or the launch error.
 // theta: n_items shells, each split in tiles of 2*cols meridian columns.
+// eneg: e^{-k} for k in [0, kExpTable), used by the exponential mask.
 hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
                         const ThetaItem *items, int n_items, int n_theta, int n_phi,
-                        const Twiddle *tw, hipStream_t stream);
+                        const Twiddle *tw, const double *eneg, hipStream_t stream);
 // phi: n_items ring pairs, `lines` of them per workgroup.
 hipError_t launch_phi(int n_line, int lines, const double *in, double *out, const PhiItem *items,
-                      int n_items, int n_theta, const Twiddle *tw, hipStream_t stream);
+                      int n_items, int n_theta, const Twiddle *tw, const double *eneg,
+                      hipStream_t stream);
 
 // Whether a (line length, launch shape) pair has a compiled kernel.
 bool theta_shape_ok(int n_line, int cols, int n_phi);
