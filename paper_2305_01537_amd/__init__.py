@@ -9,8 +9,10 @@ __all__ = ["synth"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "Batch", "SphFilter", "filter_chain", "lib", "workload_stats",
-                "SphfiltError", "status_string"):
+    if name in ("Plan", "lib", "workload_stats", "SphfiltError", "status_string"):
         from . import filter as _f
         return getattr(_f, name)
+    if name in ("SphFilter", "sph_filter", "filter_chain"):
+        from . import autograd as _a
+        return getattr(_a, name)
     raise AttributeError(name)
