@@ -150,17 +150,103 @@ int sphfilt_workload_stats(int n_r, int n_theta, int n_phi, int n_fields, const 
                            const sphfilt_cutoff *cut, sphfilt_stats *out);
 
 /*
- * Launch shape of a plan's kernels (tuning; results do not depend on it).
- *   theta_cols  meridian pairs per workgroup of the theta kernel: 8 or 16
- *               (capped at n_phi/4).  0 keeps the current value.
- *   phi_lines   ring pairs per workgroup of the phi kernel: 4, 8, 16, 32
- *               or 64 (capped so a workgroup has at most 256 lanes).  0 keeps
- *               the current value.
+ * Launch shape of a plan's kernels (tuning; results are bitwise independent
+ * of phi_lines, and theta_cols only moves round-off, see below).
+ *   theta_cols  meridian pairs per half sub-tile of the theta kernel: 8, 16,
+ *               32 or 64, at most n_phi/4 and at most 256/lanes-per-line
+ *               (16 for 2*n_theta = 256, 32 for 64 or 128, 64 for 32).  A
+ *               256-lane workgroup covers 256/lanes/theta_cols shells; two
+ *               meridian pairs theta_cols apart share one complex transform,
+ *               so changing it changes round-off only.  0 keeps the value.
+ *   phi_lines   ring pairs per workgroup of the phi kernel: 4, 8, 16, 32 or
+ *               64 (at most 256 lanes per workgroup).  0 keeps the value.
  * Returns SPHFILT_EINVAL for other values.  Not thread-safe against
  * concurrent apply calls on the same plan.
  */
 int sphfilt_plan_set_schedule(sphfilt_plan plan, int theta_cols, int phi_lines);
 int sphfilt_plan_get_schedule(sphfilt_plan plan, int *theta_cols, int *phi_lines);
+
+/* ======================================================================
+ * Batched filter: many uneven spherical patches in one launch.
+ *
+ * Each patch is filtered exactly as by its own plan (same operator, same
+ * per-line arithmetic, so bit-identical results); the batch schedules every
+ * patch's theta groups and ring-pair groups as items of one persistent
+ * kernel, replayed from a captured HIP graph.  This is the GPU counterpart of
+ * the paper's OpenMP loop over many line transforms on one rank (Sec. II.C).
+ * ====================================================================== */
+
+/* One patch: grid, fields, parities and cutoffs, as for sphfilt_plan_create. */
+typedef struct {
+    int n_r, n_theta, n_phi, n_fields;
+    const int *parity;          /* [n_fields], +1 or -1 */
+    sphfilt_cutoff cut;
+} sphfilt_patch_desc;
+
+/*
+ * Create a batch of n_patches patches on the current HIP device.
+ *   desc             [n_patches] patch descriptions; validated like
+ *                    sphfilt_plan_create (same error codes).  Read during
+ *                    the call only.
+ *   tune_cache_path  NULL: use the default schedule (no tuning).  Otherwise
+ *                    a JSON file: if it holds a schedule for this set of
+ *                    patches on this GPU architecture, that schedule is used;
+ *                    if not, the autotuner times the candidate schedules on
+ *                    scratch fields it allocates and frees, and records the
+ *                    winner there (SPHFILT_EINVAL if the file cannot be
+ *                    written).
+ * The batch owns its device tables and a small set of work counters; calls on
+ * one batch must be stream-ordered (two overlapping calls on one batch race
+ * on the counters).
+ */
+int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_desc *desc,
+                         const char *tune_cache_path);
+
+/* Release the batch (synchronises the device first).  NULL is accepted. */
+int sphfilt_batch_destroy(sphfilt_batch batch);
+
+/*
+ * Filter every patch: outs[p] = Phi(Theta(ins[p])) (adjoint = 0) or
+ * Theta(Phi(ins[p])) (adjoint != 0).
+ *   ins, outs  host arrays of n_patches device pointers, each patch's fields
+ *              in the layout of sphfilt_apply.  ins[p] == outs[p] for every
+ *              patch is the in-place fast path; an output that partially
+ *              overlaps its own input, or overlaps any other patch's input
+ *              or output, is SPHFILT_EINVAL.
+ *   stream     a hipStream_t (NULL = the null stream).
+ * The first call with a given set of pointers (and direction) captures a HIP
+ * graph (a counter-reset kernel and the persistent kernel) and caches it;
+ * later calls replay it with one graph launch.  Enqueues and returns.
+ */
+int sphfilt_batch_apply(sphfilt_batch batch, const double *const *ins, double *const *outs,
+                        int adjoint, void *stream);
+
+/* Run the autotuner now (see sphfilt_batch_create); tune_cache_path may be
+ * NULL to tune without recording.  Synchronous. */
+int sphfilt_batch_tune(sphfilt_batch batch, const char *tune_cache_path);
+
+/*
+ * Schedule of the batch kernel.
+ *   split              0: one persistent kernel; second-pass items wait on
+ *                      per-shell counters of the first pass.  1: two
+ *                      persistent kernels, first pass then second pass.
+ *   workgroups_per_cu  -1: one workgroup per work item (each takes one item
+ *                      and exits).  k > 0: a persistent grid of k workgroups
+ *                      per compute unit looping over items; 0 = the most
+ *                      that fit.
+ * get_schedule also returns the tuned time of one call in microseconds
+ * (negative when not tuned).  Results do not depend on the schedule.
+ */
+int sphfilt_batch_set_schedule(sphfilt_batch batch, int split, int workgroups_per_cu);
+int sphfilt_batch_get_schedule(sphfilt_batch batch, int *split, int *workgroups_per_cu,
+                               double *tuned_us);
+
+/* Device error word of the last call (synchronises the device): 0, or 1 if a
+ * second-pass item gave up waiting (a library bug; results are invalid). */
+int sphfilt_batch_status(sphfilt_batch batch, int *device_error);
+
+/* Work and traffic figures summed over the batch's patches (host only). */
+int sphfilt_batch_stats(sphfilt_batch batch, sphfilt_stats *out);
 
 /* Human-readable text of a status code (static storage). */
 const char *sphfilt_status_string(int status);

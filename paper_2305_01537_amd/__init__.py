@@ -9,7 +9,7 @@ __all__ = ["synth"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "lib", "workload_stats", "SphfiltError", "status_string"):
+    if name in ("Plan", "Batch", "lib", "workload_stats", "SphfiltError", "status_string"):
         from . import filter as _f
         return getattr(_f, name)
     if name in ("SphFilter", "sph_filter", "filter_chain"):

@@ -50,6 +50,16 @@ SIGNATURES = {
                                               c_int_p, ctypes.POINTER(Cutoff), ctypes.POINTER(Stats)]),
     "sphfilt_plan_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "sphfilt_plan_get_schedule": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
+    "sphfilt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                            ctypes.POINTER(PatchDesc), ctypes.c_char_p]),
+    "sphfilt_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sphfilt_batch_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
+    "sphfilt_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "sphfilt_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "sphfilt_batch_get_schedule": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_double_p]),
+    "sphfilt_batch_status": (ctypes.c_int, [ctypes.c_void_p, c_int_p]),
+    "sphfilt_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "sphfilt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sphfilt_version": (ctypes.c_char_p, []),
 }

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsphfilt.so")
-SOURCES = ["plan.cpp", "kernels.hip"]
+SOURCES = ["host_tables.cpp", "plan.cpp", "batch.cpp", "kernels.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -1,0 +1,659 @@
+// batch.cpp -- host side of the batched filter: many uneven spherical patches
+// in one persistent kernel launch, replayed from a captured HIP graph, with a
+// schedule picked by an autotuner and remembered in a JSON cache.
+//
+// The operation per patch is exactly the plan's (arXiv:2305.01537,
+// Sec. II.B): theta-pass then phi-pass (forward), or the reverse (adjoint).
+// What the batch adds is scheduling: every patch's theta groups and ring-pair
+// groups become items of one work list (see batch.hip), so small patches do
+// not leave the GPU idle and one graph launch covers all of them.
+#include "../../include/sphfilt.h"
+#include "batch_internal.h"
+#include "host_tables.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+using namespace sphfilt;
+
+namespace {
+
+constexpr int kMaxGraphs = 8;
+constexpr int kSpinLimit = 1 << 20;   // ~0.1 s of polling per shell
+
+struct PatchHost {
+    int n_r, n_theta, n_phi, n_fields;
+    HostTables tables;
+    int theta_off = 0, phi_off = 0;   // into the concatenated item arrays
+    int shell_base = 0;               // first global shell id
+    int cols = 0;                     // theta sub-tile width (meridian pairs)
+    long long n_points = 0;
+};
+
+struct ModeWork {
+    bool built = false;
+    int n_work = 0, n_first = 0;
+    BatchWork *d_work = nullptr;
+    int *d_shells = nullptr;
+    int *d_need = nullptr;
+};
+
+struct GraphEntry {
+    int mode = 0, split = 0, wpc = 0;
+    std::vector<const double *> ins;
+    std::vector<double *> outs;
+    const double **d_ins = nullptr;
+    double **d_outs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+}  // namespace
+
+struct sphfilt_batch_s {
+    int device = 0;
+    int n_cu = 0;
+    int max_wpc = 1;
+    std::string arch;
+    uint64_t signature = 0;
+    std::vector<PatchHost> patches;
+    ThetaItem *d_th = nullptr;
+    PhiItem *d_ph = nullptr;
+    BatchPatchDev *d_patches = nullptr;
+    double *d_eneg = nullptr;
+    std::map<int, Twiddle *> d_tw;
+    int n_shells_total = 0;
+    int *d_counters = nullptr;
+    int *d_tickets = nullptr;
+    int *d_error = nullptr;
+    ModeWork modes[4];
+    std::vector<GraphEntry> graphs;
+    int split = 0, wpc = -1;           // schedule: see effective_wpc
+    double tuned_us = -1.0;
+    uint64_t clock = 0;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+uint64_t fnv(uint64_t h, const void *data, size_t n)
+{
+    const unsigned char *p = (const unsigned char *)data;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+uint64_t signature(const std::string &arch, int n_patches, const sphfilt_patch_desc *d)
+{
+    uint64_t h = 1469598103934665603ULL;
+    h = fnv(h, arch.data(), arch.size());
+    h = fnv(h, &n_patches, sizeof(n_patches));
+    for (int p = 0; p < n_patches; ++p) {
+        const int dims[4] = {d[p].n_r, d[p].n_theta, d[p].n_phi, d[p].n_fields};
+        h = fnv(h, dims, sizeof(dims));
+        h = fnv(h, d[p].parity, sizeof(int) * d[p].n_fields);
+        h = fnv(h, d[p].cut.L, sizeof(double) * d[p].n_fields);
+        const int has[2] = {d[p].cut.rho != nullptr, d[p].cut.kind != nullptr};
+        h = fnv(h, has, sizeof(has));
+        if (d[p].cut.rho) h = fnv(h, d[p].cut.rho, sizeof(double) * d[p].n_r);
+        if (d[p].cut.kind) h = fnv(h, d[p].cut.kind, sizeof(int) * d[p].n_fields);
+        h = fnv(h, &d[p].cut.floor_modes, sizeof(double));
+    }
+    return h;
+}
+
+std::string hex64(uint64_t v)
+{
+    char buf[17];
+    std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)v);
+    return buf;
+}
+
+// ---- the JSON tuning cache: one entry per line -------------------------
+//   {"sphfilt_tune_cache": 1, "entries": [
+//    {"sig": "<16 hex>", "arch": "gfx950", "split": 0, "wpc": 2, "us": 812.5},
+//   ...]}
+bool cache_lookup(const char *path, const std::string &sig, int *split, int *wpc)
+{
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    const std::string key = "\"sig\": \"" + sig + "\"";
+    while (std::getline(f, line)) {
+        if (line.find(key) == std::string::npos) continue;
+        const size_t a = line.find("\"split\": "), b = line.find("\"wpc\": ");
+        if (a == std::string::npos || b == std::string::npos) return false;
+        *split = std::atoi(line.c_str() + a + 9);
+        *wpc = std::atoi(line.c_str() + b + 7);
+        return (*split == 0 || *split == 1) && *wpc >= -1 && *wpc <= 64;
+    }
+    return false;
+}
+
+bool cache_store(const char *path, const std::string &sig, const std::string &arch, int split,
+                 int wpc, double us)
+{
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            if (line.find("\"sig\": \"") == std::string::npos) continue;
+            if (line.find("\"sig\": \"" + sig + "\"") != std::string::npos) continue;
+            while (!line.empty() && (line.back() == ',' || line.back() == ']' || line.back() == '}' ||
+                                     line.back() == ' '))
+                line.pop_back();
+            keep.push_back(line + "}");
+        }
+    }
+    std::ostringstream e;
+    e << "  {\"sig\": \"" << sig << "\", \"arch\": \"" << arch << "\", \"split\": " << split
+      << ", \"wpc\": " << wpc << ", \"us\": " << us << "}";
+    keep.push_back(e.str());
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream o(tmp);
+        if (!o) return false;
+        o << "{\"sphfilt_tune_cache\": 1, \"entries\": [\n";
+        for (size_t i = 0; i < keep.size(); ++i) {
+            std::string l = keep[i];
+            if (l.rfind("  ", 0) != 0) l = "  " + l;
+            o << l << (i + 1 < keep.size() ? ",\n" : "\n");
+        }
+        o << "]}\n";
+        if (!o) return false;
+    }
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+// ---- work lists ----------------------------------------------------------
+void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
+              std::vector<BatchWork> *work, std::vector<int> *shells)
+{
+    const PatchHost &p = b->patches[(size_t)pi];
+    if (theta) {
+        const int n = all ? (int)p.tables.theta.size() : p.tables.theta_active;
+        const int C = theta_lines_per_group(2 * p.n_theta);
+        const int S = C / p.cols;
+        const int T = (p.n_phi / 2) / (2 * p.cols);
+        for (int g = 0; g * S < n; ++g) {
+            const int nv = std::min(S, n - g * S);
+            const int off = (int)shells->size();
+            for (int u = 0; u < nv; ++u)
+                shells->push_back(p.shell_base + p.tables.theta[(size_t)(g * S + u)].shell);
+            for (int tile = 0; tile < T; ++tile)
+                work->push_back(BatchWork{pi, 0, (int16_t)second, p.theta_off + g * S, (int16_t)nv,
+                                          (int16_t)tile, off, nv});
+        }
+    } else {
+        const int n = all ? (int)p.tables.phi.size() : p.tables.phi_active;
+        const int L = default_phi_lines(p.n_phi);
+        for (int c = 0; c * L < n; ++c) {
+            const int nv = std::min(L, n - c * L);
+            std::vector<int> s;
+            for (int u = 0; u < nv; ++u)
+                s.push_back(p.shell_base + p.tables.phi[(size_t)(c * L + u)].ring / p.n_theta);
+            std::sort(s.begin(), s.end());
+            s.erase(std::unique(s.begin(), s.end()), s.end());
+            const int off = (int)shells->size();
+            shells->insert(shells->end(), s.begin(), s.end());
+            work->push_back(BatchWork{pi, 1, (int16_t)second, p.phi_off + c * L, (int16_t)nv, 0, off,
+                                      (int)s.size()});
+        }
+    }
+}
+
+int build_mode(sphfilt_batch b, int mode)
+{
+    ModeWork &m = b->modes[mode];
+    if (m.built) return SPHFILT_OK;
+    const bool adjoint = mode & 1, inplace = mode & 2;
+    std::vector<BatchWork> work;
+    std::vector<int> shells;
+    for (int p = 0; p < (int)b->patches.size(); ++p)
+        add_pass(b, p, !adjoint, !inplace, false, &work, &shells);
+    const int n_first = (int)work.size();
+    for (int p = 0; p < (int)b->patches.size(); ++p)
+        add_pass(b, p, adjoint, false, true, &work, &shells);
+    std::vector<int> need((size_t)std::max(1, b->n_shells_total), 0);
+    for (int k = 0; k < n_first; ++k)
+        for (int i = 0; i < work[(size_t)k].n_shells; ++i) ++need[(size_t)shells[(size_t)(work[(size_t)k].shell_off + i)]];
+    int rc = upload(&m.d_work, work);
+    if (!rc) rc = upload(&m.d_shells, shells);
+    if (!rc) rc = upload(&m.d_need, need);
+    if (rc) return rc;
+    m.n_work = (int)work.size();
+    m.n_first = n_first;
+    m.built = true;
+    return SPHFILT_OK;
+}
+
+void free_graph(GraphEntry *g)
+{
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->d_ins) (void)hipFree((void *)g->d_ins);
+    if (g->d_outs) (void)hipFree((void *)g->d_outs);
+    *g = GraphEntry{};
+}
+
+// wpc < 0: one workgroup per item; 0: persistent, as many as fit; k: k per CU.
+int effective_wpc(sphfilt_batch b, int wpc)
+{
+    if (wpc < 0) return -1;
+    return wpc == 0 || wpc > b->max_wpc ? b->max_wpc : wpc;
+}
+
+// Record the reset kernel and the persistent kernel(s) on the capture stream.
+int record(sphfilt_batch b, const ModeWork &m, const GraphEntry &g, hipStream_t s)
+{
+    const int wpc = effective_wpc(b, g.wpc);
+    const int grid = wpc < 0 ? 0 : wpc * b->n_cu;
+    hipError_t e = launch_batch_reset(b->d_counters, b->n_shells_total, b->d_tickets, 2, b->d_error, s);
+    if (e != hipSuccess) return SPHFILT_EDEVICE;
+    if (g.split) {
+        e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
+                         m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg,
+                         0, kSpinLimit, s);
+        if (e == hipSuccess)
+            e = launch_batch(grid, m.d_work + m.n_first, m.n_work - m.n_first, b->d_patches, g.d_ins,
+                             g.d_outs, b->d_th, b->d_ph, m.d_shells, b->d_counters, m.d_need,
+                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, s);
+    } else {
+        e = launch_batch(grid, m.d_work, m.n_work, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
+                         m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg, 1,
+                         kSpinLimit, s);
+    }
+    return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
+}
+
+// The graph for (mode, pointers, schedule), captured on first use and cached.
+int get_graph(sphfilt_batch b, int mode, const double *const *ins, double *const *outs,
+              GraphEntry **out)
+{
+    const size_t P = b->patches.size();
+    for (GraphEntry &g : b->graphs) {
+        if (g.mode != mode || g.split != b->split || g.wpc != b->wpc) continue;
+        if (!std::equal(g.ins.begin(), g.ins.end(), ins) || !std::equal(g.outs.begin(), g.outs.end(), outs))
+            continue;
+        g.last_use = ++b->clock;
+        *out = &g;
+        return SPHFILT_OK;
+    }
+    int rc = build_mode(b, mode);
+    if (rc) return rc;
+    if ((int)b->graphs.size() >= kMaxGraphs) {
+        auto lru = std::min_element(b->graphs.begin(), b->graphs.end(),
+                                    [](const GraphEntry &x, const GraphEntry &y) { return x.last_use < y.last_use; });
+        free_graph(&*lru);
+        b->graphs.erase(lru);
+    }
+    GraphEntry g;
+    g.mode = mode;
+    g.split = b->split;
+    g.wpc = b->wpc;
+    g.ins.assign(ins, ins + P);
+    g.outs.assign(outs, outs + P);
+    rc = upload(&g.d_ins, g.ins);
+    if (!rc) rc = upload(&g.d_outs, g.outs);
+    if (!rc) {
+        hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) rc = SPHFILT_EDEVICE;
+        if (!rc) {
+            const int rr = record(b, b->modes[mode], g, b->capture_stream);
+            e = hipStreamEndCapture(b->capture_stream, &g.graph);
+            rc = rr ? rr : (e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE);
+        }
+        if (!rc && hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess)
+            rc = SPHFILT_EDEVICE;
+    }
+    if (rc) {
+        free_graph(&g);
+        return rc;
+    }
+    g.last_use = ++b->clock;
+    b->graphs.push_back(g);
+    *out = &b->graphs.back();
+    return SPHFILT_OK;
+}
+
+void free_batch(sphfilt_batch b)
+{
+    for (GraphEntry &g : b->graphs) free_graph(&g);
+    b->graphs.clear();
+    for (ModeWork &m : b->modes) {
+        if (m.d_work) (void)hipFree(m.d_work);
+        if (m.d_shells) (void)hipFree(m.d_shells);
+        if (m.d_need) (void)hipFree(m.d_need);
+        m = ModeWork{};
+    }
+    for (auto &kv : b->d_tw) (void)hipFree(kv.second);
+    b->d_tw.clear();
+    void *ptrs[] = {b->d_th, b->d_ph, b->d_patches, b->d_eneg, b->d_counters, b->d_tickets, b->d_error};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+}
+
+int check_pointers(sphfilt_batch b, const double *const *ins, double *const *outs, bool *inplace)
+{
+    if (!ins || !outs) return SPHFILT_EINVAL;
+    const size_t P = b->patches.size();
+    bool all_in = true;
+    for (size_t p = 0; p < P; ++p) {
+        if (!ins[p] || !outs[p]) return SPHFILT_EINVAL;
+        const uintptr_t a = (uintptr_t)ins[p], o = (uintptr_t)outs[p];
+        const size_t n = sizeof(double) * (size_t)b->patches[p].n_points;
+        if (a != o && a < o + n && o < a + n) return SPHFILT_EINVAL;
+        if (a != o) all_in = false;
+    }
+    // no patch may write into another patch's input or output
+    for (size_t p = 0; p < P; ++p) {
+        const uintptr_t o = (uintptr_t)outs[p];
+        const size_t n = sizeof(double) * (size_t)b->patches[p].n_points;
+        for (size_t q = 0; q < P; ++q) {
+            if (q == p) continue;
+            const size_t nq = sizeof(double) * (size_t)b->patches[q].n_points;
+            const uintptr_t oq = (uintptr_t)outs[q], iq = (uintptr_t)ins[q];
+            if (o < oq + nq && oq < o + n) return SPHFILT_EINVAL;
+            if (o < iq + nq && iq < o + n) return SPHFILT_EINVAL;
+        }
+    }
+    *inplace = all_in;
+    return SPHFILT_OK;
+}
+
+int launch(sphfilt_batch b, const double *const *ins, double *const *outs, int adjoint,
+           hipStream_t stream)
+{
+    bool inplace = false;
+    int rc = check_pointers(b, ins, outs, &inplace);
+    if (rc) return rc;
+    if (fault("launch")) return SPHFILT_EDEVICE;
+    const int mode = (adjoint ? 1 : 0) | (inplace ? 2 : 0);
+    GraphEntry *g = nullptr;
+    rc = get_graph(b, mode, ins, outs, &g);
+    if (rc) return rc;
+    return hipGraphLaunch(g->exec, stream) == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
+}
+
+// Time the current schedule on scratch fields: median of `reps` graph launches.
+int time_schedule(sphfilt_batch b, const std::vector<double *> &bufs, hipStream_t s, int reps, double *us)
+{
+    std::vector<const double *> ins(bufs.begin(), bufs.end());
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SPHFILT_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SPHFILT_EDEVICE; }
+    std::vector<float> t;
+    int rc = SPHFILT_OK;
+    for (int r = 0; r < reps + 2 && !rc; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = SPHFILT_EDEVICE; break; }
+        rc = launch(b, ins.data(), bufs.data(), 0, s);
+        if (rc) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = SPHFILT_EDEVICE;
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (r >= 2) t.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    *us = 1000.0 * t[t.size() / 2];
+    return SPHFILT_OK;
+}
+
+int tune(sphfilt_batch b, const char *cache_path)
+{
+    long long total = 0;
+    for (const PatchHost &p : b->patches) total += p.n_points;
+    double *scratch = nullptr;
+    hipError_t e = hipMalloc((void **)&scratch, sizeof(double) * (size_t)total);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? SPHFILT_ENOMEM : SPHFILT_EDEVICE;
+    std::vector<double *> bufs;
+    long long off = 0;
+    for (const PatchHost &p : b->patches) {
+        bufs.push_back(scratch + off);
+        off += p.n_points;
+    }
+    hipStream_t s = nullptr;
+    int rc = SPHFILT_OK;
+    if (hipMemset(scratch, 0, sizeof(double) * (size_t)total) != hipSuccess ||
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        rc = SPHFILT_EDEVICE;
+    int best_split = 0, best_wpc = -1;
+    double best = 1e300;
+    for (int split = 0; split <= 1 && !rc; ++split) {
+        for (int wpc = -1; wpc <= b->max_wpc && !rc; ++wpc) {
+            if (wpc == 0) continue;
+            b->split = split;
+            b->wpc = wpc;
+            double us = 0;
+            rc = time_schedule(b, bufs, s, 5, &us);
+            if (!rc && us < best) {
+                best = us;
+                best_split = split;
+                best_wpc = wpc;
+            }
+        }
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    // drop the graphs that point at the scratch fields
+    for (auto it = b->graphs.begin(); it != b->graphs.end();) {
+        if (!it->outs.empty() && it->outs[0] == bufs[0]) {
+            free_graph(&*it);
+            it = b->graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(scratch);
+    if (rc) return rc;
+    b->split = best_split;
+    b->wpc = best_wpc;
+    b->tuned_us = best;
+    if (cache_path && !cache_store(cache_path, hex64(b->signature), b->arch, best_split, best_wpc, best))
+        return SPHFILT_EINVAL;
+    return SPHFILT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_desc *desc,
+                         const char *tune_cache_path)
+{
+    if (!out) return SPHFILT_EINVAL;
+    *out = nullptr;
+    if (n_patches <= 0 || !desc) return SPHFILT_EINVAL;
+    long long shells = 0, th = 0, ph = 0;
+    for (int p = 0; p < n_patches; ++p) {
+        const sphfilt_patch_desc &d = desc[p];
+        const int rc = validate(d.n_r, d.n_theta, d.n_phi, d.n_fields, d.parity, &d.cut);
+        if (rc) return rc;
+        shells += (long long)d.n_fields * d.n_r;
+    }
+    if (shells > 0x7fffffffLL) return SPHFILT_EUNSUPPORTED;
+    if (fault("alloc")) return SPHFILT_ENOMEM;
+    sphfilt_batch b = new (std::nothrow) sphfilt_batch_s();
+    if (!b) return SPHFILT_ENOMEM;
+    int rc = SPHFILT_OK;
+    try {
+        std::vector<ThetaItem> all_th;
+        std::vector<PhiItem> all_ph;
+        std::vector<BatchPatchDev> pdev;
+        int shell_base = 0;
+        for (int p = 0; p < n_patches; ++p) {
+            const sphfilt_patch_desc &d = desc[p];
+            PatchHost h;
+            h.n_r = d.n_r;
+            h.n_theta = d.n_theta;
+            h.n_phi = d.n_phi;
+            h.n_fields = d.n_fields;
+            build_items(d.n_r, d.n_theta, d.n_phi, d.n_fields, d.parity, &d.cut, &h.tables);
+            h.theta_off = (int)all_th.size();
+            h.phi_off = (int)all_ph.size();
+            h.shell_base = shell_base;
+            h.cols = default_theta_cols(2 * d.n_theta, d.n_phi);
+            h.n_points = (long long)d.n_fields * d.n_r * d.n_theta * d.n_phi;
+            shell_base += d.n_fields * d.n_r;
+            all_th.insert(all_th.end(), h.tables.theta.begin(), h.tables.theta.end());
+            all_ph.insert(all_ph.end(), h.tables.phi.begin(), h.tables.phi.end());
+            b->patches.push_back(std::move(h));
+        }
+        th = (long long)all_th.size();
+        ph = (long long)all_ph.size();
+        b->n_shells_total = shell_base;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&b->device) != hipSuccess ||
+            hipGetDeviceProperties(&prop, b->device) != hipSuccess)
+            rc = SPHFILT_EDEVICE;
+        if (!rc) {
+            b->n_cu = prop.multiProcessorCount;
+            b->arch = prop.gcnArchName;
+            const size_t colon = b->arch.find(':');
+            if (colon != std::string::npos) b->arch.resize(colon);
+            b->max_wpc = batch_blocks_per_cu();
+            b->signature = signature(b->arch, n_patches, desc);
+        }
+        for (int N : {32, 64, 128, 256}) {
+            if (rc) break;
+            bool used = false;
+            for (const PatchHost &h : b->patches) used |= (2 * h.n_theta == N) || (h.n_phi == N);
+            if (!used) continue;
+            Twiddle *d = nullptr;
+            rc = upload(&d, twiddles(N));
+            if (!rc) b->d_tw[N] = d;
+        }
+        for (int p = 0; p < n_patches && !rc; ++p) {
+            const PatchHost &h = b->patches[(size_t)p];
+            pdev.push_back(BatchPatchDev{b->d_tw[2 * h.n_theta], b->d_tw[h.n_phi], h.n_theta, h.n_phi,
+                                         2 * h.n_theta, ilog2_int(h.cols)});
+        }
+        if (!rc) rc = upload(&b->d_th, all_th);
+        if (!rc) rc = upload(&b->d_ph, all_ph);
+        if (!rc) rc = upload(&b->d_patches, pdev);
+        if (!rc) rc = upload(&b->d_eneg, exp_table());
+        if (!rc) rc = upload(&b->d_counters, std::vector<int>((size_t)std::max(1, b->n_shells_total), 0));
+        if (!rc) rc = upload(&b->d_tickets, std::vector<int>(2, 0));
+        if (!rc) rc = upload(&b->d_error, std::vector<int>(1, 0));
+        if (!rc && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            rc = SPHFILT_EDEVICE;
+    } catch (const std::bad_alloc &) {
+        rc = SPHFILT_ENOMEM;
+    }
+    (void)th;
+    (void)ph;
+    if (!rc && tune_cache_path) {
+        int split = 0, wpc = 0;
+        if (cache_lookup(tune_cache_path, hex64(b->signature), &split, &wpc)) {
+            b->split = split;
+            b->wpc = wpc;
+        } else {
+            rc = tune(b, tune_cache_path);
+        }
+    }
+    if (rc) {
+        free_batch(b);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return SPHFILT_OK;
+}
+
+int sphfilt_batch_destroy(sphfilt_batch batch)
+{
+    if (!batch) return SPHFILT_OK;
+    {
+        DeviceGuard g(batch->device);
+        (void)hipDeviceSynchronize();
+        free_batch(batch);
+    }
+    delete batch;
+    return SPHFILT_OK;
+}
+
+int sphfilt_batch_apply(sphfilt_batch batch, const double *const *ins, double *const *outs,
+                        int adjoint, void *stream)
+{
+    if (!batch) return SPHFILT_EINVAL;
+    DeviceGuard g(batch->device);
+    if (!g.ok) return SPHFILT_EDEVICE;
+    return launch(batch, ins, outs, adjoint, (hipStream_t)stream);
+}
+
+int sphfilt_batch_tune(sphfilt_batch batch, const char *tune_cache_path)
+{
+    if (!batch) return SPHFILT_EINVAL;
+    DeviceGuard g(batch->device);
+    if (!g.ok) return SPHFILT_EDEVICE;
+    return tune(batch, tune_cache_path);
+}
+
+int sphfilt_batch_set_schedule(sphfilt_batch batch, int split, int workgroups_per_cu)
+{
+    if (!batch || (split != 0 && split != 1) || workgroups_per_cu < -1 ||
+        workgroups_per_cu > batch->max_wpc)
+        return SPHFILT_EINVAL;
+    batch->split = split;
+    batch->wpc = workgroups_per_cu;
+    return SPHFILT_OK;
+}
+
+int sphfilt_batch_get_schedule(sphfilt_batch batch, int *split, int *workgroups_per_cu,
+                               double *tuned_us)
+{
+    if (!batch) return SPHFILT_EINVAL;
+    if (split) *split = batch->split;
+    if (workgroups_per_cu) *workgroups_per_cu = effective_wpc(batch, batch->wpc);
+    if (tuned_us) *tuned_us = batch->tuned_us;
+    return SPHFILT_OK;
+}
+
+int sphfilt_batch_status(sphfilt_batch batch, int *device_error)
+{
+    if (!batch || !device_error) return SPHFILT_EINVAL;
+    DeviceGuard g(batch->device);
+    if (!g.ok) return SPHFILT_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return SPHFILT_EDEVICE;
+    if (hipMemcpy(device_error, batch->d_error, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return SPHFILT_EDEVICE;
+    return SPHFILT_OK;
+}
+
+int sphfilt_batch_stats(sphfilt_batch batch, sphfilt_stats *out)
+{
+    if (!batch || !out) return SPHFILT_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    for (const PatchHost &p : batch->patches) {
+        sphfilt_stats s;
+        fill_stats(p.n_r, p.n_theta, p.n_phi, p.n_fields, p.tables, &s);
+        long long *dst = (long long *)out;
+        const long long *src = (const long long *)&s;
+        for (size_t i = 0; i < sizeof(s) / sizeof(long long); ++i) dst[i] += src[i];
+    }
+    return SPHFILT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+// batch.hip -- one kernel launch that filters many uneven spherical patches
+// (each with its own grid, fields, parities and cutoffs).
+//
+// The host flattens every patch's work into one list of work items: first-pass
+// items (theta tiles for the forward filter, ring-pair groups for the
+// adjoint), then second-pass items.  Workgroups take items in list order from
+// an atomic ticket counter, so an item is only ever held by a running
+// workgroup.  Two launch forms share the item code: a persistent grid whose
+// workgroups loop over tickets, and a one-shot grid with one workgroup per
+// item.  A second-pass item of a shell must not start before every
+// first-pass item that writes that shell has finished: first-pass items bump
+// one counter per shell they wrote (after a device-scope release), and
+// second-pass items wait until the counters of the shells they touch reach
+// the host-computed totals.  Every awaited item holds a smaller ticket than the
+// waiter and never waits itself, so the wait always ends; a bounded spin
+// additionally turns a logic error into a flagged error instead of a hang.
+//
+// The per-line work is done by the same workers as the per-plan kernels
+// (line_filter.h), so a batch and per-patch plans give bit-identical results.
+#include "batch_internal.h"
+#include "line_filter.h"
+
+namespace sphfilt {
+
+// LDS of the largest worker: max over N of lines_per_256<N> * line_lds.
+constexpr int kBatchLds = 4640;
+
+template <int N>
+__device__ __forceinline__ void theta_item(const BatchWork &w, const BatchPatchDev &pd,
+                                           const double *src, double *dst,
+                                           const ThetaItem *th, const double *eneg, double *lds,
+                                           double *etab, int lane)
+{
+    theta_block<N, lines_per_256<N>()>(src, dst, th + w.first, w.n_valid, pd.cp_log2, w.tile,
+                                       pd.n_theta, pd.n_phi, pd.tw_theta, eneg, lds, etab, lane);
+}
+
+template <int N>
+__device__ __forceinline__ void phi_item(const BatchWork &w, const BatchPatchDev &pd,
+                                         const double *src, double *dst, const PhiItem *ph,
+                                         const double *eneg, double *lds, double *etab, int lane)
+{
+    phi_block<N, lines_per_256<N>()>(src, dst, ph + w.first, w.n_valid, pd.n_theta, pd.tw_phi,
+                                     eneg, lds, etab, lane);
+}
+
+struct BatchArgs {
+    const BatchWork *work;
+    int n_work;
+    const BatchPatchDev *patches;
+    const double *const *ins;
+    double *const *outs;
+    const ThetaItem *th;
+    const PhiItem *ph;
+    const int *shells;
+    int *counters;
+    const int *need;
+    int *ticket;
+    int *error;
+    const double *eneg;
+    int use_deps;
+    int spin_limit;
+};
+
+// One work item k (workgroup-uniform): wait for its shells (second pass),
+// filter, signal its shells (first pass).
+__device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, double *lds,
+                                         double *etab)
+{
+    const BatchWork w = a.work[k];
+    const BatchPatchDev pd = a.patches[w.patch];
+
+    if (a.use_deps && w.second) {
+        // wait until every first-pass item writing these shells is done
+        if (lane == 0) {
+            for (int i = 0; i < w.n_shells; ++i) {
+                const int s = a.shells[w.shell_off + i];
+                const int target = a.need[s];
+                int spins = 0;
+                while (__hip_atomic_load(a.counters + s, __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    __builtin_amdgcn_s_sleep(4);
+                    if (++spins > a.spin_limit) {
+                        atomicOr(a.error, 1);
+                        break;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    const double *src = w.second ? a.outs[w.patch] : a.ins[w.patch];
+    double *dst = a.outs[w.patch];
+    if (w.pass == 0) {
+        switch (pd.n_line) {
+        case 32: theta_item<32>(w, pd, src, dst, a.th, a.eneg, lds, etab, lane); break;
+        case 64: theta_item<64>(w, pd, src, dst, a.th, a.eneg, lds, etab, lane); break;
+        case 128: theta_item<128>(w, pd, src, dst, a.th, a.eneg, lds, etab, lane); break;
+        default: theta_item<256>(w, pd, src, dst, a.th, a.eneg, lds, etab, lane); break;
+        }
+    } else {
+        switch (pd.n_phi) {
+        case 32: phi_item<32>(w, pd, src, dst, a.ph, a.eneg, lds, etab, lane); break;
+        case 64: phi_item<64>(w, pd, src, dst, a.ph, a.eneg, lds, etab, lane); break;
+        case 128: phi_item<128>(w, pd, src, dst, a.ph, a.eneg, lds, etab, lane); break;
+        default: phi_item<256>(w, pd, src, dst, a.ph, a.eneg, lds, etab, lane); break;
+        }
+    }
+
+    if (a.use_deps && !w.second && w.n_shells > 0) {
+        // make this workgroup's stores visible device-wide, then count
+        __threadfence();
+        __syncthreads();
+        if (lane == 0)
+            for (int i = 0; i < w.n_shells; ++i)
+                __hip_atomic_fetch_add(a.counters + a.shells[w.shell_off + i], 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Take the next ticket (workgroup-uniform).
+__device__ __forceinline__ int next_ticket(int *ticket, int *cur)
+{
+    if (threadIdx.x == 0) *cur = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int k = __builtin_amdgcn_readfirstlane(*cur);
+    __syncthreads();
+    return k;
+}
+
+// One-shot form: a workgroup takes one ticket, runs that item and exits; the
+// grid has one workgroup per item.
+__global__ __launch_bounds__(256) void batch_kernel_oneshot(BatchArgs a)
+{
+    __shared__ double lds[kBatchLds];
+    __shared__ double etab[129];
+    __shared__ int cur;
+    const int k = next_ticket(a.ticket, &cur);
+    if (k < a.n_work) run_item(a, k, threadIdx.x, lds, etab);
+}
+
+// Persistent form: a fixed grid; each workgroup takes tickets until the list
+// is exhausted.  The lane index is re-read through an opaque move every item
+// so that per-lane index math is recomputed rather than kept live across
+// items (it would otherwise not fit in 256 registers).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel_persistent(
+    BatchArgs a)
+{
+    __shared__ double lds[kBatchLds];
+    __shared__ double etab[129];
+    __shared__ int cur;
+    for (;;) {
+        const int k = next_ticket(a.ticket, &cur);
+        if (k >= a.n_work) break;
+        unsigned lane;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((unsigned)threadIdx.x));
+        run_item(a, k, (int)lane, lds, etab);
+    }
+}
+
+// Zero the shell counters, the ticket counters and the error word (a kernel,
+// not a memset, so that it can sit in a captured graph).
+__global__ __launch_bounds__(256) void batch_reset_kernel(int *counters, int n_counters,
+                                                          int *tickets, int n_tickets, int *error)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_counters; i += gridDim.x * blockDim.x)
+        counters[i] = 0;
+    if (blockIdx.x == 0) {
+        if ((int)threadIdx.x < n_tickets) tickets[threadIdx.x] = 0;
+        if (threadIdx.x == 0) *error = 0;
+    }
+}
+
+hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n_tickets,
+                              int *error, hipStream_t s)
+{
+    int grid = (n_counters + 255) / 256;
+    if (grid < 1) grid = 1;
+    if (grid > 256) grid = 256;
+    batch_reset_kernel<<<grid, 256, 0, s>>>(counters, n_counters, tickets, n_tickets, error);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const BatchPatchDev *patches,
+                        const double *const *ins, double *const *outs, const ThetaItem *th,
+                        const PhiItem *ph, const int *shells, int *counters, const int *need,
+                        int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
+                        hipStream_t s)
+{
+    if (n_work <= 0) return hipSuccess;
+    const BatchArgs a{work, n_work, patches, ins, outs, th, ph, shells, counters,
+                      need, ticket, error, eneg, use_deps, spin_limit};
+    if (grid <= 0)
+        batch_kernel_oneshot<<<n_work, 256, 0, s>>>(a);
+    else
+        batch_kernel_persistent<<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent, 256, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+}  // namespace sphfilt

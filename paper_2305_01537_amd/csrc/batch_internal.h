@@ -1,0 +1,51 @@
+// batch_internal.h -- types shared by the batch host code and batch.hip.
+#pragma once
+#include "sphfilt_internal.h"
+
+#include <cstdint>
+
+namespace sphfilt {
+
+// One work item of the persistent batch kernel.
+//   pass      0: theta group (n_valid shells x one meridian tile);
+//             1: phi group (n_valid ring pairs).
+//   second    0: first pass (reads `in`, writes `out`, signals its shells);
+//             1: second pass (works in place on `out`, waits for its shells).
+//   first     index of the first item in the batch's concatenated theta or
+//             phi item array.
+//   shell_off, n_shells
+//             the distinct global shell ids this item writes (first pass) or
+//             touches (second pass), in the batch's shell list.
+struct BatchWork {
+    int32_t patch;
+    int16_t pass;
+    int16_t second;
+    int32_t first;
+    int16_t n_valid;
+    int16_t tile;
+    int32_t shell_off;
+    int32_t n_shells;
+};
+
+// Per-patch constants of the batch kernel.
+struct BatchPatchDev {
+    const Twiddle *tw_theta;
+    const Twiddle *tw_phi;
+    int32_t n_theta, n_phi;
+    int32_t n_line;       // 2 * n_theta
+    int32_t cp_log2;      // theta sub-tile width (meridian pairs), log2
+};
+
+hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n_tickets,
+                              int *error, hipStream_t s);
+// grid > 0: persistent form with `grid` workgroups; grid <= 0: one workgroup
+// per item.
+hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const BatchPatchDev *patches,
+                        const double *const *ins, double *const *outs, const ThetaItem *th,
+                        const PhiItem *ph, const int *shells, int *counters, const int *need,
+                        int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
+                        hipStream_t s);
+// Resident 256-lane workgroups of the persistent batch kernel per compute unit.
+int batch_blocks_per_cu();
+
+}  // namespace sphfilt

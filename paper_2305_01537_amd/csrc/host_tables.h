@@ -1,0 +1,60 @@
+// host_tables.h -- host-side tables shared by plans and batches.
+#pragma once
+#include "../../include/sphfilt.h"
+#include "sphfilt_internal.h"
+
+#include <vector>
+
+namespace sphfilt {
+
+// Item lists of one (n_r x n_theta x n_phi, n_fields) grid.  Items whose mask
+// is 1 on every mode come after the others (active prefix, then identity).
+struct HostTables {
+    std::vector<ThetaItem> theta;
+    std::vector<PhiItem> phi;
+    int theta_active = 0;
+    int phi_active = 0;
+};
+
+bool fault(const char *what);
+bool supported_line(int n);
+// exp(-2 pi i j / N) for j in [0, N)
+std::vector<Twiddle> twiddles(int N);
+// e^{-k} for k in [0, kExpTable)
+std::vector<double> exp_table();
+int validate(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
+             const sphfilt_cutoff *cut);
+void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
+                 const sphfilt_cutoff *cut, HostTables *h);
+void fill_stats(int n_r, int n_theta, int n_phi, int n_fields, const HostTables &h,
+                sphfilt_stats *s);
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &src)
+{
+    const size_t bytes = sizeof(T) * (src.empty() ? 1 : src.size());
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e == hipErrorOutOfMemory) { *dst = nullptr; return SPHFILT_ENOMEM; }
+    if (e != hipSuccess) { *dst = nullptr; return SPHFILT_EDEVICE; }
+    if (!src.empty() && hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return SPHFILT_EDEVICE;
+    return SPHFILT_OK;
+}
+
+// Make a device current for the duration of one call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace sphfilt

@@ -48,10 +48,15 @@ hipError_t launch_phi(int n_line, int lines, const double *in, double *out, cons
                       int n_items, int n_theta, const Twiddle *tw, const double *eneg,
                       hipStream_t stream);
 
-// Whether a (line length, launch shape) pair has a compiled kernel.
+// Launch shapes (kernels.hip).  A theta workgroup has 256 lanes holding
+// theta_lines_per_group(N) complex lines, split in sub-tiles of `cols` lines,
+// one shell per sub-tile; a phi workgroup holds `lines` ring pairs.
+int lanes_per_line(int n_line);
+int ilog2_int(int v);
+int theta_lines_per_group(int n_line);
 bool theta_shape_ok(int n_line, int cols, int n_phi);
 bool phi_shape_ok(int n_line, int lines);
-int default_theta_cols(int n_phi);
+int default_theta_cols(int n_line, int n_phi);
 int default_phi_lines(int n_line);
 
 }  // namespace sphfilt

@@ -172,5 +172,103 @@ class Plan:
         return a.value, b.value
 
 
+class Batch:
+    """Many uneven spherical patches filtered by one graph-replayed launch.
+
+    patches: a sequence of objects or dicts with n_r, n_theta, n_phi, n_fields,
+    parity, L and optionally rho, kind, floor_modes (as for Plan).
+    tune_cache: path of a JSON schedule cache; None = default schedule.  A
+    patch set not yet in the cache is autotuned (on scratch fields) at
+    creation and recorded.
+    Each patch is filtered exactly as by its own Plan (bit-identical results).
+    """
+
+    def __init__(self, patches, tune_cache: Optional[str] = None):
+        def get(p, k, d=None):
+            return p.get(k, d) if isinstance(p, dict) else getattr(p, k, d)
+        self.shapes = []
+        self._prms = []
+        n = len(patches)
+        if n == 0:
+            raise ValueError("a batch needs at least one patch")
+        descs = (_lib.PatchDesc * n)()
+        for i, p in enumerate(patches):
+            F, R, T, P = (int(get(p, "n_fields")), int(get(p, "n_r")), int(get(p, "n_theta")),
+                          int(get(p, "n_phi")))
+            prm = _Params(R, F, get(p, "parity", 1), get(p, "L", 3.0), get(p, "rho"),
+                          get(p, "kind"), get(p, "floor_modes", 2.0))
+            self._prms.append(prm)
+            self.shapes.append((F, R, T, P))
+            descs[i].n_r, descs[i].n_theta, descs[i].n_phi, descs[i].n_fields = R, T, P, F
+            descs[i].parity = prm.parity_p
+            descs[i].cut = prm.cut
+        self._descs = descs
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        path = None if tune_cache is None else str(tune_cache).encode()
+        _lib.check("sphfilt_batch_create", lib.sphfilt_batch_create(ctypes.byref(h), n, descs, path))
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.sphfilt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def apply(self, xs, outs=None, adjoint: bool = False, stream=None):
+        """outs[p] = F xs[p] (or F^T with adjoint=True); outs=xs filters in place."""
+        import torch
+        if len(xs) != len(self.shapes):
+            raise ValueError(f"expected {len(self.shapes)} tensors")
+        if outs is None:
+            outs = [torch.empty_like(x) for x in xs]
+        for x, o, shp in zip(xs, outs, self.shapes):
+            for t, name in ((x, "input"), (o, "output")):
+                if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or \
+                        t.device.type != "cuda" or tuple(t.shape) != shp or not t.is_contiguous():
+                    raise ValueError(f"{name} must be a contiguous float64 HIP tensor of shape {shp}")
+        n = len(xs)
+        ins_p = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        outs_p = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        rc = self._lib.sphfilt_batch_apply(self._h, ins_p, outs_p, 1 if adjoint else 0,
+                                           _stream_handle(xs[0], stream))
+        _lib.check("sphfilt_batch_apply", rc)
+        return outs
+
+    def tune(self, cache_path: Optional[str] = None):
+        path = None if cache_path is None else str(cache_path).encode()
+        _lib.check("sphfilt_batch_tune", self._lib.sphfilt_batch_tune(self._h, path))
+
+    def set_schedule(self, split: int, workgroups_per_cu: int):
+        _lib.check("sphfilt_batch_set_schedule",
+                   self._lib.sphfilt_batch_set_schedule(self._h, int(split), int(workgroups_per_cu)))
+
+    def get_schedule(self):
+        a, b, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _lib.check("sphfilt_batch_get_schedule",
+                   self._lib.sphfilt_batch_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                        ctypes.byref(us)))
+        return {"split": a.value, "workgroups_per_cu": b.value, "tuned_us": us.value}
+
+    def status(self) -> int:
+        e = ctypes.c_int()
+        _lib.check("sphfilt_batch_status", self._lib.sphfilt_batch_status(self._h, ctypes.byref(e)))
+        return e.value
+
+    def stats(self) -> dict:
+        st = _lib.Stats()
+        _lib.check("sphfilt_batch_stats", self._lib.sphfilt_batch_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+
 def lib():
     return _lib.load()

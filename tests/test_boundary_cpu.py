@@ -153,3 +153,49 @@ def test_workload_stats_validates_like_create():
         workload_stats(8, 16, 31, 1)
     with pytest.raises(SphfiltError):
         workload_stats(8, 16, 32, 1, parity=3)
+
+
+# ---------------------------------------------------------------------------
+# Batch creation: validation before any device call.
+# ---------------------------------------------------------------------------
+def _batch_create(L, descs_kw):
+    n = len(descs_kw)
+    descs = (L.PatchDesc * n)()
+    keep = []
+    for i, kw in enumerate(descs_kw):
+        F = kw.get("n_fields", 2)
+        par = np.ascontiguousarray(kw.get("parity", [1] * F), dtype=np.int32)
+        Lv = np.ascontiguousarray(kw.get("L", [3.0] * F), dtype=np.float64)
+        keep += [par, Lv]
+        descs[i].n_r = kw.get("n_r", 4)
+        descs[i].n_theta = kw.get("n_theta", 16)
+        descs[i].n_phi = kw.get("n_phi", 32)
+        descs[i].n_fields = F
+        descs[i].parity = par.ctypes.data_as(L.c_int_p)
+        descs[i].cut = L.Cutoff(None, Lv.ctypes.data_as(L.c_double_p), None, kw.get("floor", 2.0))
+    h = ctypes.c_void_p()
+    return L.load().sphfilt_batch_create(ctypes.byref(h), n, descs, None)
+
+
+@pytest.mark.parametrize("bad", [dict(n_phi=31), dict(parity=[1, 0]), dict(L=[3.0, -1.0]),
+                                 dict(n_r=0), dict(floor=math.nan)])
+def test_batch_create_rejects_bad_patch(L, bad):
+    assert _batch_create(L, [dict(), bad]) == L.EINVAL
+
+
+def test_batch_create_unsupported_and_empty(L):
+    assert _batch_create(L, [dict(), dict(n_theta=12)]) == L.EUNSUPPORTED
+    h = ctypes.c_void_p()
+    assert L.load().sphfilt_batch_create(ctypes.byref(h), 0, None, None) == L.EINVAL
+
+
+def test_batch_alloc_fault_injection(L, monkeypatch):
+    monkeypatch.setenv("SPHFILT_FAULT", "alloc")
+    assert _batch_create(L, [dict()]) == L.ENOMEM
+
+
+def test_batch_calls_reject_null(L):
+    lib = L.load()
+    assert lib.sphfilt_batch_apply(None, None, None, 0, None) == L.EINVAL
+    assert lib.sphfilt_batch_set_schedule(None, 0, 1) == L.EINVAL
+    assert lib.sphfilt_batch_destroy(None) == L.OK
