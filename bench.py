@@ -31,7 +31,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "share_paper_cutoff_counters.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2305_01537_amd", "csrc", f) for f in ("kernels.hip", "fft_core.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2305_01537_amd", "csrc", f)
+                  for f in ("kernels.hip", "line_filter.h", "fft_core.h", "sphfilt_internal.h")]
 
 
 def kernel_source_hash():
@@ -73,6 +74,9 @@ def parse():
     ap.add_argument("--calibrate", action="store_true",
                     help="after the timed loops, run plain copies of the workload buffer "
                          "(reference for the HBM byte counters)")
+    ap.add_argument("--patches-only", action="store_true",
+                    help="time only the 64-patch batch and print its figures as JSON "
+                         "(for profiling the batch kernel)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -126,6 +130,45 @@ def calibrate_copy(torch, x, reps=3):
     return {"copy_bytes_each": 2 * x.numel() * 8, "reps": reps}
 
 
+def bench_patches(torch, steps, stream):
+    """64 uneven patches: one tuned graph-replayed batch launch against one plan
+    (two kernel launches) per patch, forward in place, same buffers."""
+    import tempfile
+    from paper_2305_01537_amd import synth
+    from paper_2305_01537_amd.filter import Batch, Plan
+    pts = synth.patches(with_values=False)
+    g = torch.Generator(device="cuda").manual_seed(4)
+    xs = [torch.randn((p.n_fields, p.n_r, p.n_theta, p.n_phi), dtype=torch.float64, device="cuda",
+                      generator=g) for p in pts]
+    with tempfile.TemporaryDirectory() as d:
+        batch = Batch(pts, tune_cache=os.path.join(d, "tune.json"))
+    sched = batch.get_schedule()
+    st = batch.stats()
+    ms_b = time_loop(torch, lambda b: batch.apply(b, outs=b), [xs], steps, 3, stream)
+    ms_ba = time_loop(torch, lambda b: batch.apply(b, outs=b, adjoint=True), [xs], steps, 3, stream)
+    plans = [Plan(p.n_r, p.n_theta, p.n_phi, p.n_fields, parity=p.parity, L=p.L, rho=p.rho)
+             for p in pts]
+
+    def per_patch(b):
+        for pl, x in zip(plans, b):
+            pl.apply(x, out=x)
+    ms_pp = time_loop(torch, per_patch, [xs], steps, 3, stream)
+    assert batch.status() == 0
+    out = {
+        "patches": len(pts), "points": st["n_points"],
+        "algorithmic_bytes": st["bytes_forward_inplace"],
+        "batched_forward_ms": ms_b, "batched_adjoint_ms": ms_ba, "per_patch_launch_ms": ms_pp,
+        "batched_points_per_s": st["n_points"] / (ms_b * 1e-3),
+        "batched_GBps": st["bytes_forward_inplace"] / (ms_b * 1e-3) / 1e9,
+        "batched_over_per_patch_speedup": ms_pp / ms_b,
+        "schedule": sched,
+    }
+    for pl in plans:
+        pl.close()
+    batch.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -142,6 +185,9 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     t_start = time.perf_counter()
+    if args.patches_only:
+        print(json.dumps({"patches": bench_patches(torch, args.steps, stream)}), flush=True)
+        return 0
 
     log("generating the share workload (24 x 256 x 128 x 256, FP64)")
     w = synth.workload("share", L=args.L)
@@ -212,6 +258,9 @@ def main():
         }
         log(f"dense: {extra['dense']}")
         dplan.close()
+        log("timing the 64-patch batch")
+        extra["patches"] = bench_patches(torch, max(10, args.steps // 2), stream)
+        log(f"patches: {extra['patches']}")
         # streaming reference: torch's own in-place elementwise kernel on the same buffers
         ms_ref = time_loop(torch, lambda b: b.mul_(1.0), bufs, max(5, args.steps // 2), 2, stream)
         extra["stream_reference_GBps"] = 16 * points / (ms_ref * 1e-3) / 1e9
