@@ -71,14 +71,15 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
     const BatchPatchDev pd = a.patches[w.patch];
 
     if (a.use_deps && w.second) {
-        // wait until every first-pass item writing these shells is done
+        // wait until every first-pass item writing these shells is done:
+        // relaxed polling, then one device-scope acquire
         if (lane == 0) {
             for (int i = 0; i < w.n_shells; ++i) {
                 const int s = a.shells[w.shell_off + i];
                 const int target = a.need[s];
                 int spins = 0;
-                while (__hip_atomic_load(a.counters + s, __ATOMIC_ACQUIRE,
-                                         __HIP_MEMORY_SCOPE_AGENT) < target) {
+                while (__hip_atomic_load(a.counters + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                       target) {
                     __builtin_amdgcn_s_sleep(4);
                     if (++spins > a.spin_limit) {
                         atomicOr(a.error, 1);
@@ -86,6 +87,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
                     }
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
     }
@@ -109,13 +111,18 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
     }
 
     if (a.use_deps && !w.second && w.n_shells > 0) {
-        // make this workgroup's stores visible device-wide, then count
-        __threadfence();
+        // Every wave waits until its own stores have reached the L2; one lane
+        // then makes the L2 contents visible device-wide with a single
+        // device-scope release (it acts on the whole cache) and bumps the
+        // counters.
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (lane == 0)
+        if (lane == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             for (int i = 0; i < w.n_shells; ++i)
-                __hip_atomic_fetch_add(a.counters + a.shells[w.shell_off + i], 1, __ATOMIC_RELEASE,
+                __hip_atomic_fetch_add(a.counters + a.shells[w.shell_off + i], 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 

@@ -18,10 +18,17 @@ namespace sphfilt {
 // ln(0.9), the Gaussian filter's constant (eq. gaussian_filter).
 constexpr double kLog09 = -0.10536051565782630123;
 
-// Field data is streamed exactly once per pass: non-temporal loads and stores
-// keep it from displacing the small tables in the caches.
+// Field data is streamed once per pass: loads are non-temporal.  Stores of
+// the theta-pass (whose output the phi-pass reads next) and of the phi-pass
+// can each be non-temporal or cache-allocating.
 #ifndef SPHFILT_NT
 #define SPHFILT_NT 1
+#endif
+#ifndef SPHFILT_NT_STORE_THETA
+#define SPHFILT_NT_STORE_THETA 1
+#endif
+#ifndef SPHFILT_NT_STORE_PHI
+#define SPHFILT_NT_STORE_PHI 1
 #endif
 // Minimum waves per SIMD requested from the register allocator (0: compiler's
 // choice).  Bounds the VGPR count of the large-N kernels.
@@ -43,13 +50,13 @@ __device__ __forceinline__ double ld_stream(const double *p)
 #endif
 }
 
+template <bool NT = true>
 __device__ __forceinline__ void st_stream(double *p, double v)
 {
-#if SPHFILT_NT
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // Mask of one line, with the inverse transform's 1/N folded in.  v holds
@@ -297,12 +304,12 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
             constexpr int n1 = decltype(nn)::value;
             if constexpr (n1 < N1 / 2) {
                 double *row = out + base + (size_t)(N2 * n1) * n_phi;
-                st_stream(row + off_n + kr, v[n1].re);
-                st_stream(row + off_n + ki, v[n1].im);
+                st_stream<SPHFILT_NT_STORE_THETA != 0>(row + off_n + kr, v[n1].re);
+                st_stream<SPHFILT_NT_STORE_THETA != 0>(row + off_n + ki, v[n1].im);
             } else {
                 double *row = out + base + (size_t)(N - N2 * (n1 + 1)) * n_phi;
-                st_stream(row + off_s + kr, s * v[n1].re);
-                st_stream(row + off_s + ki, s * v[n1].im);
+                st_stream<SPHFILT_NT_STORE_THETA != 0>(row + off_s + kr, s * v[n1].re);
+                st_stream<SPHFILT_NT_STORE_THETA != 0>(row + off_s + ki, s * v[n1].im);
             }
         });
     } else if (valid && in != out) {
@@ -310,8 +317,8 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
             constexpr int n1 = decltype(nn)::value;
             const size_t r = n1 < N1 / 2 ? (size_t)(N2 * n1) * n_phi + off_n
                                          : (size_t)(N - N2 * (n1 + 1)) * n_phi + off_s;
-            st_stream(out + base + r + kr, ld_stream(in + base + r + kr));
-            st_stream(out + base + r + ki, ld_stream(in + base + r + ki));
+            st_stream<SPHFILT_NT_STORE_THETA != 0>(out + base + r + kr, ld_stream(in + base + r + kr));
+            st_stream<SPHFILT_NT_STORE_THETA != 0>(out + base + r + ki, ld_stream(in + base + r + ki));
         });
     }
 }
@@ -353,14 +360,14 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
     if (valid && (active || !any_active)) {
         static_for<0, N1>([&](auto nn) {
             constexpr int n1 = decltype(nn)::value;
-            st_stream(out + a + N2 * n1 + t, v[n1].re);
-            st_stream(out + b + N2 * n1 + t, v[n1].im);
+            st_stream<SPHFILT_NT_STORE_PHI != 0>(out + a + N2 * n1 + t, v[n1].re);
+            st_stream<SPHFILT_NT_STORE_PHI != 0>(out + b + N2 * n1 + t, v[n1].im);
         });
     } else if (valid && in != out) {
         static_for<0, N1>([&](auto nn) {
             constexpr int n1 = decltype(nn)::value;
-            st_stream(out + a + N2 * n1 + t, ld_stream(in + a + N2 * n1 + t));
-            st_stream(out + b + N2 * n1 + t, ld_stream(in + b + N2 * n1 + t));
+            st_stream<SPHFILT_NT_STORE_PHI != 0>(out + a + N2 * n1 + t, ld_stream(in + a + N2 * n1 + t));
+            st_stream<SPHFILT_NT_STORE_PHI != 0>(out + b + N2 * n1 + t, ld_stream(in + b + N2 * n1 + t));
         });
     }
 }
