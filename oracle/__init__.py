@@ -3,8 +3,10 @@
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  The product library never calls it.
 """
-from .oracle import (EXP, GAUSS, SHARP, mask, theta_cutoff, phi_cutoff, sin_theta,
-                     theta_pass, phi_pass, forward, adjoint, lib_path)
+from .oracle import (EXP, GAUSS, SHARP, HYBRID, mask, theta_cutoff, phi_cutoff, sin_theta,
+                     theta_pass, phi_pass, forward, adjoint, lib_path, set_detector,
+                     shock_detected, decisions)
 
-__all__ = ["EXP", "GAUSS", "SHARP", "mask", "theta_cutoff", "phi_cutoff", "sin_theta",
-           "theta_pass", "phi_pass", "forward", "adjoint", "lib_path"]
+__all__ = ["EXP", "GAUSS", "SHARP", "HYBRID", "mask", "theta_cutoff", "phi_cutoff", "sin_theta",
+           "theta_pass", "phi_pass", "forward", "adjoint", "lib_path", "set_detector",
+           "shock_detected", "decisions"]

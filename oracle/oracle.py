@@ -10,7 +10,7 @@ import os
 
 import numpy as np
 
-EXP, GAUSS, SHARP = 0, 1, 2
+EXP, GAUSS, SHARP, HYBRID = 0, 1, 2, 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libsphfilt_oracle.so")
@@ -41,6 +41,17 @@ def _load():
         lib.orc_phi_cutoff.restype = ctypes.c_double
         lib.orc_sin_theta.argtypes = [ctypes.c_int, ctypes.c_int]
         lib.orc_sin_theta.restype = ctypes.c_double
+        lib.orc_set_detector.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_set_detector.restype = None
+        lib.orc_shock_detected.argtypes = [dp, ctypes.c_int]
+        lib.orc_shock_detected.restype = ctypes.c_int
+        ucp = ctypes.POINTER(ctypes.c_ubyte)
+        lib.orc_theta_decisions.argtypes = [dp, ucp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, ip, ip]
+        lib.orc_theta_decisions.restype = ctypes.c_int
+        lib.orc_phi_decisions.argtypes = [dp, ucp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ip]
+        lib.orc_phi_decisions.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -108,3 +119,32 @@ def forward(x, parity=1, rho=None, L=3.0, kind=EXP, floor_modes=2.0, return_imag
 def adjoint(x, parity=1, rho=None, L=3.0, kind=EXP, floor_modes=2.0, return_imag=False):
     """Transpose of the double FFT filter: phi-pass, then theta-pass."""
     return _run("orc_adjoint", x, parity, rho, L, kind, floor_modes, return_imag)
+
+
+def set_detector(eps: float = 1e-12, threshold: float = 0.95) -> None:
+    """Parameters of Jameson's detector used by the hybrid filter."""
+    _load().orc_set_detector(float(eps), float(threshold))
+
+
+def shock_detected(line) -> bool:
+    g = np.ascontiguousarray(line, dtype=np.float64)
+    return bool(_load().orc_shock_detected(g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), g.size))
+
+
+def decisions(x, parity=1, kind=HYBRID):
+    """Hybrid choices (1 = Gaussian) of a theta-pass and of a phi-pass over x."""
+    x, parity, _, _, kind = _params(x, parity, None, 1.0, kind)
+    F, R, T, P = x.shape
+    th = np.zeros((F, R, P // 2), dtype=np.uint8)
+    ph = np.zeros((F, R, T), dtype=np.uint8)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ucp = ctypes.POINTER(ctypes.c_ubyte)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib = _load()
+    rc = lib.orc_theta_decisions(x.ctypes.data_as(dp), th.ctypes.data_as(ucp), F, R, T, P,
+                                 parity.ctypes.data_as(ip), kind.ctypes.data_as(ip))
+    rc |= lib.orc_phi_decisions(x.ctypes.data_as(dp), ph.ctypes.data_as(ucp), F, R, T, P,
+                                kind.ctypes.data_as(ip))
+    if rc:
+        raise ValueError("decision export failed")
+    return th, ph

@@ -26,6 +26,13 @@
  *   Masks: exponential filter (eq. exp_filter), Gaussian filter
  *     (eq. gaussian_filter) and the spectrally sharp low-pass the paper
  *     mentions beside them.
+ *   Hybrid filter (the automatic switch at the end of Sec. II.B): for each
+ *     extended theta line and each phi ring of a field, Jameson's shock
+ *     detector sigma_i = |u_{i-1} - 2 u_i + u_{i+1}| /
+ *     (|u_{i-1}| + 2|u_i| + |u_{i+1}| + eps) is evaluated at every cell
+ *     (periodic neighbours along the line); if any cell has
+ *     sigma >= threshold (0.95 in the paper) the line takes the Gaussian
+ *     filter, otherwise the exponential one.
  *
  * Every DFT here is the direct O(N^2) sum with the angle index reduced
  * exactly, (q*n) mod N, before the table lookup.  Nothing is skipped: lines
@@ -47,12 +54,34 @@
 #define ORC_EXP   0
 #define ORC_GAUSS 1
 #define ORC_SHARP 2
+#define ORC_HYBRID 3
 
 #define ORC_OK     0
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
 
 static const double ORC_PI = 3.14159265358979323846264338327950288;
+
+/* Detector parameters of the hybrid filter: epsilon and the threshold. */
+static double orc_det_eps = 1e-12;
+static double orc_det_threshold = 0.95;
+
+void orc_set_detector(double eps, double threshold)
+{
+    orc_det_eps = eps;
+    orc_det_threshold = threshold;
+}
+
+/* Jameson's detector on one periodic line: 1 if any cell has sigma >= threshold. */
+int orc_shock_detected(const double *g, int N)
+{
+    for (int n = 0; n < N; ++n) {
+        const double a = g[(n - 1 + N) % N], b = g[n], c = g[(n + 1) % N];
+        const double sigma = fabs(a - 2.0 * b + c) / (fabs(a) + 2.0 * fabs(b) + fabs(c) + orc_det_eps);
+        if (sigma >= orc_det_threshold) return 1;
+    }
+    return 0;
+}
 
 /* Filter function f(qhat, c) for a mode of magnitude qhat and cutoff c. */
 double orc_mask(int kind, double qhat, double c)
@@ -130,6 +159,15 @@ static void orc_filter_line(int N, const double *g, double *out, int kind, doubl
     }
 }
 
+/* The extended line of meridian pair (k, k + n_phi/2) of one shell X:
+ * g[n] = X[n][k] for n < n_theta, s X[2 n_theta - 1 - n][k + n_phi/2] after. */
+static void orc_extended_line(const double *X, int k, int n_theta, int n_phi, double s, double *g)
+{
+    const int N = 2 * n_theta, half = n_phi / 2;
+    for (int n = 0; n < n_theta; ++n) g[n] = X[(int64_t)n * n_phi + k];
+    for (int n = n_theta; n < N; ++n) g[n] = s * X[(int64_t)(N - 1 - n) * n_phi + k + half];
+}
+
 static void orc_tables(int N, double *ct, double *st)
 {
     for (int m = 0; m < N; ++m) {
@@ -145,7 +183,7 @@ static int orc_check(int n_fields, int n_r, int n_theta, int n_phi, const int *p
     if (!parity || !rho || !L || !kind) return ORC_EINVAL;
     for (int f = 0; f < n_fields; ++f) {
         if (parity[f] != 1 && parity[f] != -1) return ORC_EINVAL;
-        if (kind[f] < ORC_EXP || kind[f] > ORC_SHARP) return ORC_EINVAL;
+        if (kind[f] < ORC_EXP || kind[f] > ORC_HYBRID) return ORC_EINVAL;
     }
     return ORC_OK;
 }
@@ -182,11 +220,11 @@ int orc_theta_pass(const double *in, double *out, int n_fields, int n_r, int n_t
             const double s = (double)parity[f];
             const double *X = in + ((int64_t)f * n_r + i) * (int64_t)n_theta * n_phi;
             double *Y = out + ((int64_t)f * n_r + i) * (int64_t)n_theta * n_phi;
-            for (int n = 0; n < n_theta; ++n) g[n] = X[(int64_t)n * n_phi + k];
-            for (int n = n_theta; n < N; ++n)
-                g[n] = s * X[(int64_t)(N - 1 - n) * n_phi + k + half];
+            orc_extended_line(X, k, n_theta, n_phi, s, g);
             double c = orc_theta_cutoff(rho[i], L[f], floor_modes);
-            orc_filter_line(N, g, o, kind[f], c, ct, st, Gre, Gim, &imag_max);
+            int k_line = kind[f];
+            if (k_line == ORC_HYBRID) k_line = orc_shock_detected(g, N) ? ORC_GAUSS : ORC_EXP;
+            orc_filter_line(N, g, o, k_line, c, ct, st, Gre, Gim, &imag_max);
             for (int n = 0; n < n_theta; ++n) Y[(int64_t)n * n_phi + k] = o[n];
             for (int n = n_theta; n < N; ++n) Y[(int64_t)(N - 1 - n) * n_phi + k + half] = s * o[n];
         }
@@ -222,7 +260,10 @@ int orc_phi_pass(const double *in, double *out, int n_fields, int n_r, int n_the
             int i = (int)((ring / n_theta) % n_r);
             int f = (int)(ring / ((int64_t)n_theta * n_r));
             double c = orc_phi_cutoff(rho[i], L[f], j, n_theta, floor_modes);
-            orc_filter_line(N, in + ring * n_phi, out + ring * n_phi, kind[f], c, ct, st, Gre,
+            int k_line = kind[f];
+            if (k_line == ORC_HYBRID)
+                k_line = orc_shock_detected(in + ring * n_phi, N) ? ORC_GAUSS : ORC_EXP;
+            orc_filter_line(N, in + ring * n_phi, out + ring * n_phi, k_line, c, ct, st, Gre,
                             Gim, &imag_max);
         }
         free(Gre); free(Gim);
@@ -268,4 +309,40 @@ int orc_adjoint(const double *in, double *out, int n_fields, int n_r, int n_thet
     free(tmp);
     if (imag_max_out) *imag_max_out = a > b ? a : b;
     return rc;
+}
+
+/* The hybrid filter's choices for one pass over `in`, without filtering:
+ * theta: dec[(f n_r + i) n_phi/2 + k] for the extended line of meridian pair k;
+ * phi:   dec[(f n_r + i) n_theta + j] for ring j.  1 = Gaussian, 0 = exponential.
+ * Fields whose kind is not hybrid get 0. */
+int orc_theta_decisions(const double *in, unsigned char *dec, int n_fields, int n_r, int n_theta,
+                        int n_phi, const int *parity, const int *kind)
+{
+    if (n_fields <= 0 || n_r <= 0 || n_theta <= 0 || n_phi <= 0 || (n_phi & 1)) return ORC_EINVAL;
+    const int N = 2 * n_theta, half = n_phi / 2;
+    double *g = malloc(sizeof(double) * N);
+    if (!g) return ORC_ENOMEM;
+    for (int f = 0; f < n_fields; ++f)
+        for (int i = 0; i < n_r; ++i)
+            for (int k = 0; k < half; ++k) {
+                const double s = (double)parity[f];
+                const double *X = in + ((int64_t)f * n_r + i) * (int64_t)n_theta * n_phi;
+                orc_extended_line(X, k, n_theta, n_phi, s, g);
+                dec[((int64_t)f * n_r + i) * half + k] =
+                    (unsigned char)(kind[f] == ORC_HYBRID && orc_shock_detected(g, N));
+            }
+    free(g);
+    return ORC_OK;
+}
+
+int orc_phi_decisions(const double *in, unsigned char *dec, int n_fields, int n_r, int n_theta,
+                      int n_phi, const int *kind)
+{
+    if (n_fields <= 0 || n_r <= 0 || n_theta <= 0 || n_phi <= 0) return ORC_EINVAL;
+    const int64_t n_rings = (int64_t)n_fields * n_r * n_theta;
+    for (int64_t ring = 0; ring < n_rings; ++ring) {
+        const int f = (int)(ring / ((int64_t)n_theta * n_r));
+        dec[ring] = (unsigned char)(kind[f] == ORC_HYBRID && orc_shock_detected(in + ring * n_phi, n_phi));
+    }
+    return ORC_OK;
 }

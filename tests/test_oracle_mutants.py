@@ -21,6 +21,7 @@ WRAPPER = os.path.join(ROOT, "oracle", "oracle.py")
 MUTANTS = {
     "extension sign dropped": ("g[n] = s * X[", "g[n] = X["),
     "extension not reversed": ("g[n] = s * X[(int64_t)(N - 1 - n) * n_phi", "g[n] = s * X[(int64_t)(n - n_theta) * n_phi"),
+    "extension without the half-turn in phi": ("* n_phi + k + half];\n}", "* n_phi + k];\n}"),
     "write-back sign dropped": ("k + half] = s * o[n]", "k + half] = o[n]"),
     "passes swapped in forward": (
         "int rc = orc_theta_pass(in, tmp, n_fields, n_r, n_theta, n_phi, parity, rho, L, kind,\n"
@@ -40,6 +41,10 @@ MUTANTS = {
     "gaussian constant": ("exp(log(0.9) * u * u)", "exp(log(0.8) * u * u)"),
     "floor ignored": ("return c > floor_modes ? c : floor_modes;\n}\n\n/* sin", "return c;\n}\n\n/* sin"),
     "phi cutoff without sin(theta)": ("double c = 2.0 * rho * orc_sin_theta(j, n_theta) * L;", "double c = 2.0 * rho * L;"),
+    "detector never fires": ("if (sigma >= orc_det_threshold) return 1;", "if (sigma > 2.0) return 1;"),
+    "detector not periodic": ("const double a = g[(n - 1 + N) % N], b = g[n], c = g[(n + 1) % N];",
+                              "const double a = g[n > 0 ? n - 1 : 0], b = g[n], c = g[n + 1 < N ? n + 1 : N - 1];"),
+    "detector ignores the centre weight": ("fabs(a - 2.0 * b + c)", "fabs(a - b + c)"),
     "mode index not reduced": ("int m = (int)(((int64_t)q * n) % N);\n            re += g[n]", "int m = (int)(((int64_t)q * n + n) % N);\n            re += g[n]"),
 }
 
@@ -75,6 +80,11 @@ def _pin_cases():
         lambda m: P.test_p8_paper_constants(m),
         lambda m: P.test_p8_cutoff_depends_on_r_and_latitude(m),
         lambda m: [P.test_p10_library_fft_matches(m, k) for k in (0, 1, 2)],
+        lambda m: P.test_hybrid_smooth_fields_take_the_exponential_filter(m),
+        lambda m: P.test_hybrid_ring_with_a_jump_takes_the_gaussian(m),
+        lambda m: P.test_hybrid_theta_decision_uses_the_extended_line(m),
+        lambda m: P.test_hybrid_grid_scale_oscillation_is_detected(m),
+        lambda m: P.test_hybrid_detector_is_periodic_and_has_a_threshold(m),
     ]
 
 

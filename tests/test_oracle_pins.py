@@ -436,3 +436,129 @@ def test_p10_library_fft_matches_grmhd_slice(oracle_mod):
     ref = fft_phi_pass(fft_theta_pass(w.x, w.parity, w.rho, L, kinds), w.parity, w.rho, L, kinds)
     got = oracle_mod.forward(w.x, parity=w.parity, rho=w.rho, L=L, kind=kinds)
     assert rel_err(got, ref) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# Hybrid filter (the automatic switch at the end of Sec. II.B): Jameson's
+# detector picks the Gaussian filter for a line with a discontinuity and the
+# exponential filter otherwise.
+# --------------------------------------------------------------------------
+HYBRID = 3
+
+
+def fft_hybrid_phi_pass(x, rho, L, kinds_per_ring):
+    """phi-pass with a given kind per ring (library FFT)."""
+    F, R, T, P = x.shape
+    out = np.empty_like(x)
+    for f in range(F):
+        mm = mmax_np(rho, L[f], T)
+        for i in range(R):
+            for j in range(T):
+                k = kinds_per_ring[f, i, j]
+                out[f, i, j] = fft_filter_lines(x[f, i, j][None, :], np.array([mm[i, j]]), k)[0]
+    return out
+
+
+def smooth_fields(shape, seed=20):
+    """Positive, even-parity fields that are smooth at the grid scale (l <= 4)."""
+    rng = np.random.default_rng(seed)
+    F, R, T, P = shape
+    theta, phi = synth.theta_grid(T), synth.phi_grid(P)
+    x = np.empty(shape)
+    for f in range(F):
+        for i in range(R):
+            x[f, i] = 3.0 + synth.angular_sum(rng, 4, theta, phi, lambda l: 0.2)
+    assert x.min() > 0.5
+    return x, np.ones(F, dtype=np.int32)
+
+
+def test_hybrid_smooth_fields_take_the_exponential_filter(oracle_mod):
+    x, parity = smooth_fields((3, 6, 32, 64))
+    th, ph = oracle_mod.decisions(x, parity=parity)
+    assert th.sum() == 0 and ph.sum() == 0
+    for fn in (oracle_mod.forward, oracle_mod.adjoint, oracle_mod.theta_pass, oracle_mod.phi_pass):
+        a = fn(x, parity=parity, L=0.6, kind=HYBRID)
+        b = fn(x, parity=parity, L=0.6, kind=EXP)
+        assert np.array_equal(a, b)
+
+
+def test_hybrid_grid_scale_oscillation_is_detected(oracle_mod):
+    # Jameson's detector also fires on sign-alternating (two-cell) oscillations
+    N = 32
+    g = 1.0 + 0.01 * np.cos(2 * np.pi * np.arange(N) / N)
+    g[10:13] = [0.8, -1.6, 1.9]
+    assert oracle_mod.shock_detected(g)
+
+
+def test_hybrid_ring_with_a_jump_takes_the_gaussian(oracle_mod):
+    rng = np.random.default_rng(21)
+    T, P = 16, 32
+    theta, phi = synth.theta_grid(T), synth.phi_grid(P)
+    x = np.broadcast_to(real_ylm(3, 1, theta, phi), (1, 3, T, P)).copy()
+    # (shell, ring) replaced by a step out of zero; sigma = J / (4|A| + J) at a
+    # jump J on top of a level A, so only jumps from near zero reach 0.95
+    jumps = [(0, 2), (2, 9)]
+    for i, j in jumps:
+        x[0, i, j, :] = np.where(np.arange(P) < P // 3, 0.0, 2.0)
+    rho = np.array([0.5, 1.5, 2.5])
+    got = oracle_mod.phi_pass(x, parity=1, rho=rho, L=0.6, kind=HYBRID)
+    kinds = np.zeros((1, 3, T), dtype=int)
+    for i, j in jumps:
+        kinds[0, i, j] = GAUSS
+    ref = fft_hybrid_phi_pass(x, rho, np.array([0.6]), kinds)
+    assert rel_err(got, ref) <= 1e-13
+    _, ph = oracle_mod.decisions(x, parity=1)
+    assert sorted(zip(*np.nonzero(ph[0]))) == jumps
+
+
+def jameson_np(g, eps=1e-12, thr=0.95):
+    a, c = np.roll(g, 1, axis=-1), np.roll(g, -1, axis=-1)
+    sig = np.abs(a - 2 * g + c) / (np.abs(a) + 2 * np.abs(g) + np.abs(c) + eps)
+    return (sig >= thr).any(axis=-1)
+
+
+def test_hybrid_theta_decision_uses_the_extended_line(oracle_mod):
+    # a +1 / -1 pair of values on meridians k and k + n_phi/2 next to the north
+    # pole, zero elsewhere: the extended line has them adjacent, times the
+    # parity sign.  Even parity: -1 next to +1 (sigma = 1 at the pole);
+    # odd parity: +1 next to +1 (the jump to zero still fires one cell on).
+    rng = np.random.default_rng(22)
+    x = rng.uniform(0.5, 1.5, (2, 3, 8, 16)) * np.where(rng.random((2, 3, 8, 16)) < 0.3, 0.0, 1.0)
+    for parity in (np.array([1, 1]), np.array([-1, -1]), np.array([1, -1])):
+        th, _ = oracle_mod.decisions(x, parity=parity)
+        for f in range(2):
+            h = x.shape[3] // 2
+            ext = np.concatenate([x[f, :, :, :h], parity[f] * x[f, :, ::-1, h:]], axis=1)  # (R, 2T, h)
+            assert np.array_equal(th[f].astype(bool), jameson_np(np.swapaxes(ext, 1, 2)))
+    # and the filtered result follows the decisions line by line
+    par = np.array([1, -1])
+    got = oracle_mod.theta_pass(x, parity=par, L=0.6, kind=HYBRID)
+    g = oracle_mod.theta_pass(x, parity=par, L=0.6, kind=GAUSS)
+    e = oracle_mod.theta_pass(x, parity=par, L=0.6, kind=EXP)
+    th, _ = oracle_mod.decisions(x, parity=par)
+    h = x.shape[3] // 2
+    pick = np.concatenate([th, th], axis=-1)[:, :, None, :].astype(bool)
+    assert np.array_equal(got, np.where(pick, g, e))
+
+
+def test_hybrid_detector_is_periodic_and_has_a_threshold(oracle_mod):
+    N = 32
+    n = np.arange(N)
+    # a jump J on a level A gives sigma = J / (4A + J): 0.95 needs J >= 76 A
+    base = np.where(n < N // 2, 1.0, 1.0 + 75.0)
+    assert not oracle_mod.shock_detected(base)
+    assert oracle_mod.shock_detected(np.where(n < N // 2, 1.0, 1.0 + 77.0))
+    assert not oracle_mod.shock_detected(np.cos(2 * np.pi * n / N) + 3.0)
+    assert not oracle_mod.shock_detected(np.zeros(N))
+    # a geometric ramp: sigma ~ 0.04 inside, ~1 only where the line wraps
+    # around (its largest value next to its smallest)
+    ramp = 1e-3 * 1.5 ** n
+    assert oracle_mod.shock_detected(ramp)
+    assert not oracle_mod.shock_detected(np.r_[ramp[: N // 2], ramp[: N // 2][::-1]])   # same values, no wrap jump
+    step = np.where(n < N // 2, 0.0, 1.0)
+    assert oracle_mod.shock_detected(step)          # sigma = 1 / (1 + eps) at the step
+    oracle_mod.set_detector(1e-12, 1.0)              # a threshold above 1/(1+eps) never fires on it
+    try:
+        assert not oracle_mod.shock_detected(step)
+    finally:
+        oracle_mod.set_detector()
