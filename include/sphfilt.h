@@ -55,6 +55,8 @@ extern "C" {
 #define SPHFILT_EXP   0   /* f = 1 for |l| <= c, exp(-(|l| - c)) above        (eq. exp_filter)      */
 #define SPHFILT_GAUSS 1   /* f = exp(log(0.9) (|l| / (c + 1))^2)               (eq. gaussian_filter) */
 #define SPHFILT_SHARP 2   /* f = 1 for |l| <= c, 0 above (sharp low-pass named beside eq. exp_filter) */
+#define SPHFILT_HYBRID 3  /* per line: GAUSS if Jameson's detector fires, else EXP (the automatic
+                             switch at the end of Sec. II.B); see sphfilt_cutoff and sphfilt_apply_ex */
 
 typedef struct sphfilt_plan_s  *sphfilt_plan;   /* opaque; immutable after create */
 typedef struct sphfilt_batch_s *sphfilt_batch;  /* opaque; see sphfilt_batch_create */
@@ -66,8 +68,17 @@ typedef struct sphfilt_batch_s *sphfilt_batch;  /* opaque; see sphfilt_batch_cre
  *                cell-centred grid rho_i = i + 1/2.
  *   L            [n_fields] the cutoff scale cal-L, each finite and > 0
  *                (the paper uses 3 for metric fields and 12 for matter).
- *   kind         [n_fields] SPHFILT_EXP / GAUSS / SHARP, or NULL => all EXP.
+ *   kind         [n_fields] SPHFILT_EXP / GAUSS / SHARP / HYBRID, or NULL =>
+ *                all EXP.
  *   floor_modes  finite, >= 0: the lowest cutoff; 2 in the paper.
+ *   detector_eps, detector_threshold
+ *                Jameson's detector of the hybrid kind: a line (an extended
+ *                theta line or a phi ring, periodic) takes the Gaussian
+ *                filter if some cell has
+ *                |u_{i-1} - 2u_i + u_{i+1}| / (|u_{i-1}| + 2|u_i| + |u_{i+1}| + eps)
+ *                >= threshold.  0 selects the defaults eps = 1e-12 and
+ *                threshold = 0.95 (the paper's); otherwise finite, eps >= 0,
+ *                threshold > 0.  Unused unless some field is HYBRID.
  * The arrays are read during the call only; the plan keeps its own copy.
  */
 typedef struct {
@@ -75,6 +86,8 @@ typedef struct {
     const double *L;
     const int    *kind;
     double        floor_modes;
+    double        detector_eps;
+    double        detector_threshold;
 } sphfilt_cutoff;
 
 /*
@@ -133,6 +146,23 @@ int sphfilt_apply(sphfilt_plan plan, const double *in, double *out, void *stream
 /* out = Theta(Phi(in)) = F^T in: the transpose of sphfilt_apply (each pass is
  * real symmetric).  Arguments and errors as for sphfilt_apply. */
 int sphfilt_apply_adjoint(sphfilt_plan plan, const double *in, double *out, void *stream);
+
+/*
+ * The filter with control over the hybrid kind's decisions.
+ *   adjoint     0: Phi(Theta(in)); 1: Theta(Phi(in)).
+ *   theta_dec   device bytes [n_fields][n_r][n_phi/2], one per extended theta
+ *               line (meridian pair k); phi_dec: [n_fields][n_r][n_theta], one
+ *               per ring.  1 = Gaussian, 0 = exponential; entries of
+ *               non-hybrid fields are not touched.
+ *   replay      0: hybrid lines decide from the data each pass sees; if the
+ *               buffers are not NULL the decisions are written there.
+ *               1: hybrid lines use the decisions in the buffers (both
+ *               required): the filter is then linear, and the adjoint call
+ *               with the decisions of a forward call is its exact transpose.
+ * Other arguments and errors as for sphfilt_apply.
+ */
+int sphfilt_apply_ex(sphfilt_plan plan, const double *in, double *out, int adjoint,
+                     unsigned char *theta_dec, unsigned char *phi_dec, int replay, void *stream);
 
 /* The theta-pass alone (Sec. II.B, theta FFT filter on extended lines).
  * Arguments and errors as for sphfilt_apply. */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsphfilt.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
-EXP, GAUSS, SHARP = 0, 1, 2
+EXP, GAUSS, SHARP, HYBRID = 0, 1, 2, 3
 
 c_int_p = ctypes.POINTER(ctypes.c_int)
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -18,7 +18,8 @@ c_double_p = ctypes.POINTER(ctypes.c_double)
 
 class Cutoff(ctypes.Structure):
     _fields_ = [("rho", c_double_p), ("L", c_double_p), ("kind", c_int_p),
-                ("floor_modes", ctypes.c_double)]
+                ("floor_modes", ctypes.c_double), ("detector_eps", ctypes.c_double),
+                ("detector_threshold", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -43,6 +44,8 @@ SIGNATURES = {
     "sphfilt_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sphfilt_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sphfilt_apply_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sphfilt_apply_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "sphfilt_apply_theta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sphfilt_apply_phi": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sphfilt_plan_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),

@@ -4,7 +4,10 @@ The filter F = Phi o Theta is linear, and each pass is a real symmetric
 operator (a block-diagonal set of real circulants, conjugated by the
 pole-extension permutation for Theta), so the vector-Jacobian product of F is
 F^T = Theta o Phi: the library's adjoint call.  Nothing needs to be saved for
-the backward.
+the backward -- except with hybrid fields, whose per-line choice between the
+Gaussian and the exponential filter depends on the data: the forward records
+the choices and the backward applies the transpose of the filter with those
+choices frozen (the filter is piecewise linear in its input).
 
 filter_chain applies y_{k+1} = tanh(F y_k) K times, optionally under
 activation checkpointing (each application's input is kept; the forward of
@@ -24,11 +27,21 @@ class SphFilter(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x: torch.Tensor, plan: Plan) -> torch.Tensor:
         ctx.plan = plan
-        return plan.apply(x.contiguous())
+        x = x.contiguous()
+        if plan.has_hybrid:
+            th, ph = plan.decision_buffers(x.device)
+            y = plan.apply_ex(x, theta_dec=th, phi_dec=ph, replay=False)
+            ctx.save_for_backward(th, ph)
+            return y
+        return plan.apply(x)
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        return ctx.plan.apply_adjoint(grad_out.contiguous()), None
+        g = grad_out.contiguous()
+        if ctx.plan.has_hybrid:
+            th, ph = ctx.saved_tensors
+            return ctx.plan.apply_ex(g, adjoint=True, theta_dec=th, phi_dec=ph, replay=True), None
+        return ctx.plan.apply_adjoint(g), None
 
 
 def sph_filter(x: torch.Tensor, plan: Plan) -> torch.Tensor:

@@ -81,6 +81,7 @@ struct sphfilt_batch_s {
     ModeWork modes[4];
     std::vector<GraphEntry> graphs;
     int split = 0, wpc = -1;           // schedule: see effective_wpc
+    int hybrid = 0;                    // some patch has a hybrid field
     double tuned_us = -1.0;
     uint64_t clock = 0;
     hipStream_t capture_stream = nullptr;
@@ -113,6 +114,8 @@ uint64_t signature(const std::string &arch, int n_patches, const sphfilt_patch_d
         if (d[p].cut.rho) h = fnv(h, d[p].cut.rho, sizeof(double) * d[p].n_r);
         if (d[p].cut.kind) h = fnv(h, d[p].cut.kind, sizeof(int) * d[p].n_fields);
         h = fnv(h, &d[p].cut.floor_modes, sizeof(double));
+        h = fnv(h, &d[p].cut.detector_eps, sizeof(double));
+        h = fnv(h, &d[p].cut.detector_threshold, sizeof(double));
     }
     return h;
 }
@@ -269,15 +272,15 @@ int record(sphfilt_batch b, const ModeWork &m, const GraphEntry &g, hipStream_t 
     if (g.split) {
         e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
                          m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg,
-                         0, kSpinLimit, s);
+                         0, kSpinLimit, b->hybrid, s);
         if (e == hipSuccess)
             e = launch_batch(grid, m.d_work + m.n_first, m.n_work - m.n_first, b->d_patches, g.d_ins,
                              g.d_outs, b->d_th, b->d_ph, m.d_shells, b->d_counters, m.d_need,
-                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, s);
+                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid, s);
     } else {
         e = launch_batch(grid, m.d_work, m.n_work, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
                          m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg, 1,
-                         kSpinLimit, s);
+                         kSpinLimit, b->hybrid, s);
     }
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
@@ -533,7 +536,9 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
             b->arch = prop.gcnArchName;
             const size_t colon = b->arch.find(':');
             if (colon != std::string::npos) b->arch.resize(colon);
-            b->max_wpc = batch_blocks_per_cu();
+            for (int p = 0; p < n_patches; ++p)
+                b->hybrid |= hybrid_args(&desc[p].cut, desc[p].n_fields).present;
+            b->max_wpc = batch_blocks_per_cu(b->hybrid);
             b->signature = signature(b->arch, n_patches, desc);
         }
         for (int N : {32, 64, 128, 256}) {
@@ -547,8 +552,11 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
         }
         for (int p = 0; p < n_patches && !rc; ++p) {
             const PatchHost &h = b->patches[(size_t)p];
+            const HybridArgs ha = hybrid_args(&desc[p].cut, h.n_fields);
+            b->hybrid |= ha.present;
             pdev.push_back(BatchPatchDev{b->d_tw[2 * h.n_theta], b->d_tw[h.n_phi], h.n_theta, h.n_phi,
-                                         2 * h.n_theta, ilog2_int(h.cols)});
+                                         2 * h.n_theta, ilog2_int(h.cols), ha.eps, ha.threshold,
+                                         ha.present, 0});
         }
         if (!rc) rc = upload(&b->d_th, all_th);
         if (!rc) rc = upload(&b->d_ph, all_ph);

@@ -25,23 +25,31 @@ namespace sphfilt {
 // LDS of the largest worker: max over N of lines_per_256<N> * line_lds.
 constexpr int kBatchLds = 4640;
 
-template <int N>
+// Hybrid lines in a batch decide from their data; decisions are not recorded.
+__device__ __forceinline__ HybridArgs batch_hybrid(const BatchPatchDev &pd)
+{
+    return HybridArgs{pd.det_eps, pd.det_threshold, nullptr, 0, pd.hybrid};
+}
+
+template <int N, bool HYB>
 __device__ __forceinline__ void theta_item(const BatchWork &w, const BatchPatchDev &pd,
                                            const double *src, double *dst,
                                            const ThetaItem *th, const double *eneg, double *lds,
-                                           double *etab, int lane)
+                                           double *etab, int *flags, int lane)
 {
-    theta_block<N, lines_per_256<N>()>(src, dst, th + w.first, w.n_valid, pd.cp_log2, w.tile,
-                                       pd.n_theta, pd.n_phi, pd.tw_theta, eneg, lds, etab, lane);
+    theta_block<N, lines_per_256<N>(), HYB>(src, dst, th + w.first, w.n_valid, pd.cp_log2, w.tile,
+                                       pd.n_theta, pd.n_phi, pd.tw_theta, eneg, lds, etab, flags,
+                                       batch_hybrid(pd), lane);
 }
 
-template <int N>
+template <int N, bool HYB>
 __device__ __forceinline__ void phi_item(const BatchWork &w, const BatchPatchDev &pd,
                                          const double *src, double *dst, const PhiItem *ph,
-                                         const double *eneg, double *lds, double *etab, int lane)
+                                         const double *eneg, double *lds, double *etab, int *flags,
+                                         int lane)
 {
-    phi_block<N, lines_per_256<N>()>(src, dst, ph + w.first, w.n_valid, pd.n_theta, pd.tw_phi,
-                                     eneg, lds, etab, lane);
+    phi_block<N, lines_per_256<N>(), HYB>(src, dst, ph + w.first, w.n_valid, pd.n_theta, pd.tw_phi,
+                                     eneg, lds, etab, flags, batch_hybrid(pd), lane);
 }
 
 struct BatchArgs {
@@ -64,8 +72,9 @@ struct BatchArgs {
 
 // One work item k (workgroup-uniform): wait for its shells (second pass),
 // filter, signal its shells (first pass).
+template <bool HYB>
 __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, double *lds,
-                                         double *etab)
+                                         double *etab, int *flags)
 {
     const BatchWork w = a.work[k];
     const BatchPatchDev pd = a.patches[w.patch];
@@ -96,17 +105,17 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
     double *dst = a.outs[w.patch];
     if (w.pass == 0) {
         switch (pd.n_line) {
-        case 32: theta_item<32>(w, pd, src, dst, a.th, a.eneg, lds, etab, lane); break;
-        case 64: theta_item<64>(w, pd, src, dst, a.th, a.eneg, lds, etab, lane); break;
-        case 128: theta_item<128>(w, pd, src, dst, a.th, a.eneg, lds, etab, lane); break;
-        default: theta_item<256>(w, pd, src, dst, a.th, a.eneg, lds, etab, lane); break;
+        case 32: theta_item<32, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+        case 64: theta_item<64, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+        case 128: theta_item<128, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+        default: theta_item<256, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
         }
     } else {
         switch (pd.n_phi) {
-        case 32: phi_item<32>(w, pd, src, dst, a.ph, a.eneg, lds, etab, lane); break;
-        case 64: phi_item<64>(w, pd, src, dst, a.ph, a.eneg, lds, etab, lane); break;
-        case 128: phi_item<128>(w, pd, src, dst, a.ph, a.eneg, lds, etab, lane); break;
-        default: phi_item<256>(w, pd, src, dst, a.ph, a.eneg, lds, etab, lane); break;
+        case 32: phi_item<32, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+        case 64: phi_item<64, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+        case 128: phi_item<128, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+        default: phi_item<256, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
         }
     }
 
@@ -138,31 +147,35 @@ __device__ __forceinline__ int next_ticket(int *ticket, int *cur)
 
 // One-shot form: a workgroup takes one ticket, runs that item and exits; the
 // grid has one workgroup per item.
+template <bool HYB>
 __global__ __launch_bounds__(256) void batch_kernel_oneshot(BatchArgs a)
 {
     __shared__ double lds[kBatchLds];
     __shared__ double etab[129];
+    __shared__ int flags[64];
     __shared__ int cur;
     const int k = next_ticket(a.ticket, &cur);
-    if (k < a.n_work) run_item(a, k, threadIdx.x, lds, etab);
+    if (k < a.n_work) run_item<HYB>(a, k, threadIdx.x, lds, etab, flags);
 }
 
 // Persistent form: a fixed grid; each workgroup takes tickets until the list
 // is exhausted.  The lane index is re-read through an opaque move every item
 // so that per-lane index math is recomputed rather than kept live across
 // items (it would otherwise not fit in 256 registers).
+template <bool HYB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel_persistent(
     BatchArgs a)
 {
     __shared__ double lds[kBatchLds];
     __shared__ double etab[129];
+    __shared__ int flags[64];
     __shared__ int cur;
     for (;;) {
         const int k = next_ticket(a.ticket, &cur);
         if (k >= a.n_work) break;
         unsigned lane;
         asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((unsigned)threadIdx.x));
-        run_item(a, k, (int)lane, lds, etab);
+        run_item<HYB>(a, k, (int)lane, lds, etab, flags);
     }
 }
 
@@ -193,23 +206,28 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
                         const double *const *ins, double *const *outs, const ThetaItem *th,
                         const PhiItem *ph, const int *shells, int *counters, const int *need,
                         int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
-                        hipStream_t s)
+                        int hybrid, hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
     const BatchArgs a{work, n_work, patches, ins, outs, th, ph, shells, counters,
                       need, ticket, error, eneg, use_deps, spin_limit};
-    if (grid <= 0)
-        batch_kernel_oneshot<<<n_work, 256, 0, s>>>(a);
-    else
-        batch_kernel_persistent<<<grid, 256, 0, s>>>(a);
+    if (grid <= 0) {
+        if (hybrid) batch_kernel_oneshot<true><<<n_work, 256, 0, s>>>(a);
+        else batch_kernel_oneshot<false><<<n_work, 256, 0, s>>>(a);
+    } else {
+        if (hybrid) batch_kernel_persistent<true><<<grid, 256, 0, s>>>(a);
+        else batch_kernel_persistent<false><<<grid, 256, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
-int batch_blocks_per_cu()
+int batch_blocks_per_cu(int hybrid)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent, 256, 0) != hipSuccess)
-        return 1;
+    const hipError_t e =
+        hybrid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<true>, 256, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<false>, 256, 0);
+    if (e != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 

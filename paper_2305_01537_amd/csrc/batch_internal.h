@@ -34,6 +34,9 @@ struct BatchPatchDev {
     int32_t n_theta, n_phi;
     int32_t n_line;       // 2 * n_theta
     int32_t cp_log2;      // theta sub-tile width (meridian pairs), log2
+    double det_eps, det_threshold;   // hybrid kind: Jameson's detector
+    int32_t hybrid;       // some field of the patch is hybrid
+    int32_t pad;
 };
 
 hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n_tickets,
@@ -44,8 +47,9 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
                         const double *const *ins, double *const *outs, const ThetaItem *th,
                         const PhiItem *ph, const int *shells, int *counters, const int *need,
                         int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
-                        hipStream_t s);
-// Resident 256-lane workgroups of the persistent batch kernel per compute unit.
-int batch_blocks_per_cu();
+                        int hybrid, hipStream_t s);
+// Resident 256-lane workgroups of the persistent batch kernel per compute
+// unit (hybrid: the variant with the hybrid filter's detector).
+int batch_blocks_per_cu(int hybrid);
 
 }  // namespace sphfilt

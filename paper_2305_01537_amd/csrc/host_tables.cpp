@@ -73,10 +73,12 @@ int validate(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
     if (n_phi % 2 != 0) return SPHFILT_EINVAL;
     if (!parity || !cut || !cut->L) return SPHFILT_EINVAL;
     if (!std::isfinite(cut->floor_modes) || cut->floor_modes < 0.0) return SPHFILT_EINVAL;
+    if (!std::isfinite(cut->detector_eps) || cut->detector_eps < 0.0) return SPHFILT_EINVAL;
+    if (!std::isfinite(cut->detector_threshold) || cut->detector_threshold < 0.0) return SPHFILT_EINVAL;
     for (int f = 0; f < n_fields; ++f) {
         if (parity[f] != 1 && parity[f] != -1) return SPHFILT_EINVAL;
         if (!std::isfinite(cut->L[f]) || !(cut->L[f] > 0.0)) return SPHFILT_EINVAL;
-        if (cut->kind && (cut->kind[f] < SPHFILT_EXP || cut->kind[f] > SPHFILT_SHARP))
+        if (cut->kind && (cut->kind[f] < SPHFILT_EXP || cut->kind[f] > SPHFILT_HYBRID))
             return SPHFILT_EINVAL;
     }
     if (cut->rho)
@@ -101,14 +103,16 @@ void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parit
             const double rho = cut->rho ? cut->rho[i] : (double)i + 0.5;
             double c = 2.0 * rho * L;
             if (!(c > cut->floor_modes)) c = cut->floor_modes;
-            const bool ident = kind != SPHFILT_GAUSS && c >= (double)n_theta;
+            // Gaussian and hybrid lines always act (the Gaussian damps every l != 0)
+            const bool may_skip = kind == SPHFILT_EXP || kind == SPHFILT_SHARP;
+            const bool ident = may_skip && c >= (double)n_theta;
             const ThetaItem t{f * n_r + i, base_flags | (ident ? kFlagIdentity : 0), c};
             (ident ? ti : ta).push_back(t);
             for (int j = 0; j < n_theta / 2; ++j) {
                 const double s = std::sin(((double)j + 0.5) * kPi / (double)n_theta);
                 double m = 2.0 * rho * s * L;
                 if (!(m > cut->floor_modes)) m = cut->floor_modes;
-                const bool pid = kind != SPHFILT_GAUSS && m >= (double)(n_phi / 2);
+                const bool pid = may_skip && m >= (double)(n_phi / 2);
                 const PhiItem p{(f * n_r + i) * n_theta + j, base_flags | (pid ? kFlagIdentity : 0), m};
                 (pid ? pi : pa).push_back(p);
             }
@@ -120,6 +124,15 @@ void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parit
     h->theta.insert(h->theta.end(), ti.begin(), ti.end());
     h->phi = std::move(pa);
     h->phi.insert(h->phi.end(), pi.begin(), pi.end());
+}
+
+HybridArgs hybrid_args(const sphfilt_cutoff *cut, int n_fields)
+{
+    HybridArgs h{};
+    h.eps = cut->detector_eps > 0.0 ? cut->detector_eps : 1e-12;
+    h.threshold = cut->detector_threshold > 0.0 ? cut->detector_threshold : 0.95;
+    for (int f = 0; f < n_fields && cut->kind; ++f) h.present |= cut->kind[f] == SPHFILT_HYBRID;
+    return h;
 }
 
 void fill_stats(int n_r, int n_theta, int n_phi, int n_fields, const HostTables &h, sphfilt_stats *s)

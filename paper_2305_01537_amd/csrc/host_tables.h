@@ -26,6 +26,8 @@ int validate(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
              const sphfilt_cutoff *cut);
 void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
                  const sphfilt_cutoff *cut, HostTables *h);
+// Detector parameters (defaults for zeros) and whether any field is hybrid.
+HybridArgs hybrid_args(const sphfilt_cutoff *cut, int n_fields);
 void fill_stats(int n_r, int n_theta, int n_phi, int n_fields, const HostTables &h,
                 sphfilt_stats *s);
 

@@ -104,6 +104,67 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[N1], int t, int kind, doubl
     }
 }
 
+// Mask of a complex line whose two real lines take different kinds (the
+// hybrid filter can pick the Gaussian for one and the exponential for the
+// other).  With z = a + i b and Z its transform, A and B (the transforms of a
+// and b) are (Z[q] + conj Z[-q]) / 2 and (Z[q] - conj Z[-q]) / 2i, so
+//   f_a A + i f_b B = (f_a + f_b)/2 Z[q] + (f_a - f_b)/2 conj Z[N - q].
+// Bin N - q lives on another lane: every lane publishes its bins through the
+// line's LDS region L (natural order, real then imaginary parts).  Lines with
+// ka == kb get plain f Z.  All lanes of the workgroup call this together.
+template <int N1, int N2>
+__device__ __forceinline__ double kind_mask(int kind, int qhat, int m, double g_exp,
+                                            double inv_c1, const double *etab)
+{
+    constexpr double inv_n = 1.0 / (N1 * N2);
+    if (kind == 1) {
+        const double u = (double)qhat * inv_c1;
+        return exp(kLog09 * u * u) * inv_n;
+    }
+    if (qhat <= m) return inv_n;
+    return (kind == 0 ? g_exp : 0.0) * etab[qhat - m - 1];
+}
+
+template <int N1, int N2>
+__device__ __forceinline__ void apply_mask_pair(cplx (&v)[N1], int t, int ka, int kb, double c,
+                                                const double *etab, double *L)
+{
+    constexpr int N = N1 * N2;
+    constexpr int R = N1 / N2;
+    constexpr double inv_n = 1.0 / N;
+    const int m = c >= (double)N ? N : (int)floor(c);
+    const double g_exp = exp((c - (double)m) - 1.0) * inv_n;
+    const double inv_c1 = 1.0 / (c + 1.0);
+    static_for<0, 2>([&](auto part) {
+        constexpr bool im = decltype(part)::value == 1;
+        static_for<0, R>([&](auto rr) {
+            constexpr int r = decltype(rr)::value;
+            static_for<0, N2>([&](auto kk) {
+                constexpr int k2 = decltype(kk)::value;
+                L[t + N2 * r + N1 * k2] = im ? v[r * N2 + k2].im : v[r * N2 + k2].re;
+            });
+        });
+        __syncthreads();
+        static_for<0, R>([&](auto rr) {
+            constexpr int r = decltype(rr)::value;
+            static_for<0, N2>([&](auto kk) {
+                constexpr int k2 = decltype(kk)::value;
+                const int q = t + N2 * r + N1 * k2;
+                const int qhat = q <= N / 2 ? q : N - q;
+                const double fa = kind_mask<N1, N2>(ka, qhat, m, g_exp, inv_c1, etab);
+                const double fb = ka == kb ? fa : kind_mask<N1, N2>(kb, qhat, m, g_exp, inv_c1, etab);
+                const double alpha = 0.5 * (fa + fb), beta = 0.5 * (fa - fb);
+                const double partner = L[(N - q) & (N - 1)];
+                if constexpr (im)
+                    v[r * N2 + k2].im = alpha * v[r * N2 + k2].im - beta * partner;
+                else
+                    v[r * N2 + k2].re = alpha * v[r * N2 + k2].re + beta * partner;
+            });
+        });
+        __syncthreads();
+    });
+}
+
 // LDS doubles per line: an N1 x (N2 + 1) padded tile plus one double, so that
 // consecutive lines start on different banks.
 template <int N1, int N2>
@@ -194,9 +255,10 @@ __device__ __forceinline__ void twiddle_powers(cplx (&v)[NV], const Twiddle *__r
 // holds x[N2 n1 + t] in v[n1]); on return v holds the filtered values at the
 // same positions.  Every lane of the workgroup calls this together.
 // etab: e^{-k}, k <= N/2, in LDS, written before the first barrier here.
-template <int N1, int N2>
-__device__ __forceinline__ void filter_line(cplx (&v)[N1], int t, int kind, double c, double *L,
-                                            const Twiddle *__restrict__ tw, const double *etab)
+template <int N1, int N2, bool HYB>
+__device__ __forceinline__ void filter_line(cplx (&v)[N1], int t, int kind, int kind_b, bool mixed,
+                                            double c, double *L, const Twiddle *__restrict__ tw,
+                                            const double *etab)
 {
     constexpr int R = N1 / N2;
     static_assert(N1 % N2 == 0, "lane count must divide the register count");
@@ -208,7 +270,17 @@ __device__ __forceinline__ void filter_line(cplx (&v)[N1], int t, int kind, doub
     // N2-point DFTs over n2: v[r N2 + k2] = X[k1 + N1 k2], k1 = t + N2 r
     static_for<0, R>([&](auto rr) { dft_reg<N2, false, decltype(rr)::value * N2>(v); });
 
-    apply_mask<N1, N2>(v, t, kind, c, etab);
+    // kind: the real part's filter; kind_b: the imaginary part's.  mixed
+    // (workgroup-uniform) is set when some line of the workgroup has two;
+    // only the hybrid-capable variant (HYB) carries that code.
+    if constexpr (HYB) {
+        if (mixed)
+            apply_mask_pair<N1, N2>(v, t, kind, kind_b, c, etab, L);
+        else
+            apply_mask<N1, N2>(v, t, kind, c, etab);
+    } else {
+        apply_mask<N1, N2>(v, t, kind, c, etab);
+    }
 
     // inverse: N2-point inverse DFTs, conjugate twiddles W_N^{-n2 k1},
     // transpose back, N1-point inverse DFTs
@@ -236,6 +308,75 @@ template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
 template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
 
 
+// Jameson's detector sigma_i = |u_{i-1} - 2u_i + u_{i+1}| /
+// (|u_{i-1}| + 2|u_i| + |u_{i+1}| + eps) on the two real lines packed in v
+// (periodic along the line).  Returns bit 0 if any cell of the real-part
+// line has sigma >= threshold, bit 1 for the imaginary-part line.  Lanes
+// exchange neighbours through the line's LDS region L and combine their
+// findings in *flag (this line's LDS word).  All lanes call this together;
+// `check` says whether this lane's line needs the detector at all.
+template <int N1, int N2>
+__device__ __forceinline__ int detect_shocks(const cplx (&v)[N1], int t, double *L, int *flag,
+                                             bool check, double eps, double threshold)
+{
+    constexpr int N = N1 * N2;
+    if (t == 0) *flag = 0;
+    int bits = 0;
+    static_for<0, 2>([&](auto part) {
+        constexpr bool im = decltype(part)::value == 1;
+        static_for<0, N1>([&](auto nn) {
+            constexpr int n1 = decltype(nn)::value;
+            L[N2 * n1 + t] = im ? v[n1].im : v[n1].re;
+        });
+        __syncthreads();
+        if (check) {
+            static_for<0, N1>([&](auto nn) {
+                constexpr int n1 = decltype(nn)::value;
+                const int n = N2 * n1 + t;
+                const double a = L[(n + N - 1) & (N - 1)];
+                const double b = im ? v[n1].im : v[n1].re;
+                const double c = L[(n + 1) & (N - 1)];
+                const double sigma = fabs(a - 2.0 * b + c) / (fabs(a) + 2.0 * fabs(b) + fabs(c) + eps);
+                if (sigma >= threshold) bits |= im ? 2 : 1;
+            });
+        }
+        __syncthreads();
+    });
+    if (bits) atomicOr(flag, bits);
+    __syncthreads();
+    return *flag;
+}
+
+// The two kinds of a packed line: a hybrid line takes the Gaussian where its
+// detector fired (or its recorded decision says so), else the exponential.
+// dec_a / dec_b: byte offsets of the two real lines in h.dec.
+template <int N1, int N2>
+__device__ __forceinline__ void hybrid_kinds(const cplx (&v)[N1], int t, double *L, int *flag,
+                                             bool active, int kind, size_t dec_a, size_t dec_b,
+                                             const HybridArgs &h, int *ka, int *kb, bool *mixed)
+{
+    *ka = kind;
+    *kb = kind;
+    *mixed = false;
+    if (!h.present) return;
+    const bool hybrid = active && kind == 3;
+    int bits = 0;
+    if (h.replay) {
+        if (hybrid) bits = (h.dec[dec_a] ? 1 : 0) | (h.dec[dec_b] ? 2 : 0);
+    } else {
+        bits = detect_shocks<N1, N2>(v, t, L, flag, hybrid, h.eps, h.threshold);
+        if (hybrid && h.dec && t == 0) {
+            h.dec[dec_a] = (unsigned char)(bits & 1);
+            h.dec[dec_b] = (unsigned char)((bits >> 1) & 1);
+        }
+    }
+    if (hybrid) {
+        *ka = (bits & 1) ? 1 : 0;
+        *kb = (bits & 2) ? 1 : 0;
+    }
+    *mixed = __syncthreads_or(*ka != *kb) != 0;
+}
+
 // Lanes per line and lines per 256-lane workgroup for each supported N.
 template <int N>
 constexpr int lines_per_256() { return 256 / Split<N>::N2; }
@@ -251,13 +392,13 @@ constexpr int lines_per_256() { return 256 / Split<N>::N2; }
 // poles).  Lanes walk the meridians fastest, so loads and stores touch whole
 // row segments.  All lanes of the workgroup must call this together.
 // ---------------------------------------------------------------------------
-template <int N, int C>
+template <int N, int C, bool HYB>
 __device__ __forceinline__ void theta_block(const double *in, double *out,
                                             const ThetaItem *__restrict__ items, int n_valid,
                                             int cp_log2, int tile, int n_theta, int n_phi,
                                             const Twiddle *__restrict__ tw,
                                             const double *__restrict__ eneg, double *lds,
-                                            double *etab, int lane)
+                                            double *etab, int *flags, const HybridArgs &h, int lane)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
     static_assert(C * N2 == 256, "theta workgroups have 256 lanes");
@@ -296,9 +437,16 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
     // Identity lines sharing a workgroup with filtered ones run through the
     // transform (the barriers are workgroup-wide) but their result is dropped;
     // they are copied exactly from `in`.  That only happens out of place.
-    if (any_active)
-        filter_line<N1, N2>(v, t, it.flags & kKindMask, active ? it.c : INFINITY,
-                            lds + p * line_lds<N1, N2>(), tw, etab);
+    if (any_active) {
+        double *L = lds + p * line_lds<N1, N2>();
+        const size_t dline = (size_t)it.shell * (size_t)half;
+        int ka = it.flags & kKindMask, kb = ka;
+        bool mixed = false;
+        if constexpr (HYB)
+            hybrid_kinds<N1, N2>(v, t, L, flags + p, active, ka, dline + kr, dline + ki, h, &ka,
+                                 &kb, &mixed);
+        filter_line<N1, N2, HYB>(v, t, ka, kb, mixed, active ? it.c : INFINITY, L, tw, etab);
+    }
     if (valid && (active || !any_active)) {
         static_for<0, N1>([&](auto nn) {
             constexpr int n1 = decltype(nn)::value;
@@ -329,12 +477,12 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
 // mirror ring n_theta-1-j of the same shell (imaginary part), which shares
 // m_max.  Lines p >= n_valid are idle.  All lanes call this together.
 // ---------------------------------------------------------------------------
-template <int N, int LINES>
+template <int N, int LINES, bool HYB>
 __device__ __forceinline__ void phi_block(const double *in, double *out,
                                           const PhiItem *__restrict__ items, int n_valid,
                                           int n_theta, const Twiddle *__restrict__ tw,
                                           const double *__restrict__ eneg, double *lds,
-                                          double *etab, int lane)
+                                          double *etab, int *flags, const HybridArgs &h, int lane)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
     const int t = lane % N2, p = lane / N2;
@@ -354,9 +502,16 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
         v[n1] = valid ? cplx{ld_stream(in + a + N2 * n1 + t), ld_stream(in + b + N2 * n1 + t)}
                       : cplx{0.0, 0.0};
     });
-    if (any_active)
-        filter_line<N1, N2>(v, t, it.flags & kKindMask, active ? it.c : INFINITY,
-                            lds + p * line_lds<N1, N2>(), tw, etab);
+    if (any_active) {
+        double *L = lds + p * line_lds<N1, N2>();
+        const size_t ring_b = (size_t)it.ring + (size_t)(n_theta - 1 - 2 * j);
+        int ka = it.flags & kKindMask, kb = ka;
+        bool mixed = false;
+        if constexpr (HYB)
+            hybrid_kinds<N1, N2>(v, t, L, flags + p, active, ka, (size_t)it.ring, ring_b, h, &ka,
+                                 &kb, &mixed);
+        filter_line<N1, N2, HYB>(v, t, ka, kb, mixed, active ? it.c : INFINITY, L, tw, etab);
+    }
     if (valid && (active || !any_active)) {
         static_for<0, N1>([&](auto nn) {
             constexpr int n1 = decltype(nn)::value;

@@ -43,6 +43,7 @@ struct sphfilt_plan_s {
     HostTables host;
     DeviceTables dev;
     int theta_cols, phi_lines;
+    HybridArgs hybrid;      // detector parameters; dec / replay set per call
 };
 
 namespace {
@@ -59,17 +60,28 @@ void free_device(DeviceTables *d)
 
 enum class Pass { Theta, Phi };
 
-int run_pass(sphfilt_plan p, Pass which, const double *in, double *out, bool all_items, hipStream_t s)
+struct Decisions {
+    unsigned char *theta = nullptr;
+    unsigned char *phi = nullptr;
+    int replay = 0;
+};
+
+int run_pass(sphfilt_plan p, Pass which, const double *in, double *out, bool all_items,
+             const Decisions &d, hipStream_t s)
 {
     hipError_t e;
+    HybridArgs h = p->hybrid;
+    h.replay = d.replay;
     if (which == Pass::Theta) {
+        h.dec = d.theta;
         const int n = all_items ? (int)p->host.theta.size() : p->host.theta_active;
         e = launch_theta(2 * p->n_theta, p->theta_cols, in, out, p->dev.theta, n, p->n_theta,
-                         p->n_phi, p->dev.tw_theta, p->dev.eneg, s);
+                         p->n_phi, p->dev.tw_theta, p->dev.eneg, h, s);
     } else {
+        h.dec = d.phi;
         const int n = all_items ? (int)p->host.phi.size() : p->host.phi_active;
         e = launch_phi(p->n_phi, p->phi_lines, in, out, p->dev.phi, n, p->n_theta, p->dev.tw_phi,
-                       p->dev.eneg, s);
+                       p->dev.eneg, h, s);
     }
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
@@ -86,7 +98,8 @@ int check_call(sphfilt_plan p, const double *in, double *out)
 
 // Two passes in the given order.  Out of place, the first pass runs over all
 // items (copying identity lines) and the second works in place on `out`.
-int apply_two(sphfilt_plan p, Pass first, Pass second, const double *in, double *out, void *stream)
+int apply_two(sphfilt_plan p, Pass first, Pass second, const double *in, double *out,
+              const Decisions &d, void *stream)
 {
     int rc = check_call(p, in, out);
     if (rc) return rc;
@@ -94,9 +107,9 @@ int apply_two(sphfilt_plan p, Pass first, Pass second, const double *in, double 
     if (!g.ok) return SPHFILT_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     const bool inplace = in == out;
-    rc = run_pass(p, first, in, out, !inplace, s);
+    rc = run_pass(p, first, in, out, !inplace, d, s);
     if (rc) return rc;
-    return run_pass(p, second, out, out, false, s);
+    return run_pass(p, second, out, out, false, d, s);
 }
 
 int apply_one(sphfilt_plan p, Pass which, const double *in, double *out, void *stream)
@@ -105,7 +118,7 @@ int apply_one(sphfilt_plan p, Pass which, const double *in, double *out, void *s
     if (rc) return rc;
     DeviceGuard g(p->device);
     if (!g.ok) return SPHFILT_EDEVICE;
-    return run_pass(p, which, in, out, in != out, (hipStream_t)stream);
+    return run_pass(p, which, in, out, in != out, Decisions{}, (hipStream_t)stream);
 }
 
 }  // namespace
@@ -143,6 +156,7 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
     p->n_phi = n_phi;
     p->n_fields = n_fields;
     p->theta_cols = default_theta_cols(2 * n_theta, n_phi);
+    p->hybrid = hybrid_args(cut, n_fields);
     p->phi_lines = default_phi_lines(n_phi);
     try {
         build_items(n_r, n_theta, n_phi, n_fields, parity, cut, &p->host);
@@ -177,12 +191,21 @@ int sphfilt_plan_destroy(sphfilt_plan plan)
 
 int sphfilt_apply(sphfilt_plan plan, const double *in, double *out, void *stream)
 {
-    return apply_two(plan, Pass::Theta, Pass::Phi, in, out, stream);
+    return apply_two(plan, Pass::Theta, Pass::Phi, in, out, Decisions{}, stream);
 }
 
 int sphfilt_apply_adjoint(sphfilt_plan plan, const double *in, double *out, void *stream)
 {
-    return apply_two(plan, Pass::Phi, Pass::Theta, in, out, stream);
+    return apply_two(plan, Pass::Phi, Pass::Theta, in, out, Decisions{}, stream);
+}
+
+int sphfilt_apply_ex(sphfilt_plan plan, const double *in, double *out, int adjoint,
+                     unsigned char *theta_dec, unsigned char *phi_dec, int replay, void *stream)
+{
+    if (replay && (!theta_dec || !phi_dec)) return SPHFILT_EINVAL;
+    const Decisions d{theta_dec, phi_dec, replay ? 1 : 0};
+    return adjoint ? apply_two(plan, Pass::Phi, Pass::Theta, in, out, d, stream)
+                   : apply_two(plan, Pass::Theta, Pass::Phi, in, out, d, stream);
 }
 
 int sphfilt_apply_theta(sphfilt_plan plan, const double *in, double *out, void *stream)

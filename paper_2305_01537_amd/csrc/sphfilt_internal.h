@@ -30,6 +30,17 @@ struct PhiItem {
     double c;              // m_max
 };
 
+// Hybrid-filter arguments of a pass (the automatic exponential/Gaussian
+// switch of Sec. II.B).  dec: one byte per real line, 1 = Gaussian; with
+// replay the decisions are read from it, otherwise they are detected and,
+// if dec is not null, recorded.  present: the launch has hybrid lines.
+struct HybridArgs {
+    double eps, threshold;
+    unsigned char *dec;
+    int replay;
+    int present;
+};
+
 // Length of the e^{-k} table: covers k <= N/2 for every supported N.
 constexpr int kExpTable = 512;
 
@@ -42,11 +53,12 @@ struct Twiddle {
 // eneg: e^{-k} for k in [0, kExpTable), used by the exponential mask.
 hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
                         const ThetaItem *items, int n_items, int n_theta, int n_phi,
-                        const Twiddle *tw, const double *eneg, hipStream_t stream);
+                        const Twiddle *tw, const double *eneg, const HybridArgs &h,
+                        hipStream_t stream);
 // phi: n_items ring pairs, `lines` of them per workgroup.
 hipError_t launch_phi(int n_line, int lines, const double *in, double *out, const PhiItem *items,
                       int n_items, int n_theta, const Twiddle *tw, const double *eneg,
-                      hipStream_t stream);
+                      const HybridArgs &h, hipStream_t stream);
 
 // Launch shapes (kernels.hip).  A theta workgroup has 256 lanes holding
 // theta_lines_per_group(N) complex lines, split in sub-tiles of `cols` lines,

@@ -18,7 +18,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import EXP, GAUSS, SHARP, SphfiltError, status_string  # noqa: F401
+from ._lib import EXP, GAUSS, HYBRID, SHARP, SphfiltError, status_string  # noqa: F401
 
 
 def _as_int_array(v, n, name):
@@ -38,7 +38,8 @@ def _as_double_array(v, n, name):
 class _Params:
     """Host copies of the per-field / per-shell parameters and their C views."""
 
-    def __init__(self, n_r, n_fields, parity, L, rho, kind, floor_modes):
+    def __init__(self, n_r, n_fields, parity, L, rho, kind, floor_modes, detector_eps=0.0,
+                 detector_threshold=0.0):
         self.parity = _as_int_array(parity, n_fields, "parity")
         self.L = _as_double_array(L, n_fields, "L")
         self.rho = None if rho is None else _as_double_array(rho, n_r, "rho")
@@ -47,7 +48,8 @@ class _Params:
             None if self.rho is None else self.rho.ctypes.data_as(_lib.c_double_p),
             self.L.ctypes.data_as(_lib.c_double_p),
             None if self.kind is None else self.kind.ctypes.data_as(_lib.c_int_p),
-            float(floor_modes))
+            float(floor_modes), float(detector_eps), float(detector_threshold))
+        self.has_hybrid = self.kind is not None and bool((self.kind == HYBRID).any())
 
     @property
     def parity_p(self):
@@ -55,9 +57,10 @@ class _Params:
 
 
 def workload_stats(n_r, n_theta, n_phi, n_fields, parity=1, L=3.0, rho=None, kind=None,
-                   floor_modes=2.0) -> dict:
+                   floor_modes=2.0, detector_eps=0.0, detector_threshold=0.0) -> dict:
     """Active lines and algorithmic HBM bytes of a filter call (host only)."""
-    prm = _Params(n_r, n_fields, parity, L, rho, kind, floor_modes)
+    prm = _Params(n_r, n_fields, parity, L, rho, kind, floor_modes, detector_eps,
+                  detector_threshold)
     st = _lib.Stats()
     _lib.check("sphfilt_workload_stats",
                _lib.load().sphfilt_workload_stats(n_r, n_theta, n_phi, n_fields, prm.parity_p,
@@ -76,15 +79,20 @@ class Plan:
     """A filter plan for n_fields FP64 fields on an n_r x n_theta x n_phi grid.
 
     parity: +1/-1 per field (axis parity); L: cutoff scale per field;
-    rho: r/dr_min per shell (None: i + 1/2); kind: EXP/GAUSS/SHARP per field
-    (None: EXP); floor_modes: the cutoff floor (2 in the paper).
+    rho: r/dr_min per shell (None: i + 1/2); kind: EXP/GAUSS/SHARP/HYBRID per
+    field (None: EXP); floor_modes: the cutoff floor (2 in the paper);
+    detector_eps / detector_threshold: Jameson's detector of the HYBRID kind
+    (0: the defaults 1e-12 and 0.95).
     The plan's tables live on the current HIP device.
     """
 
     def __init__(self, n_r: int, n_theta: int, n_phi: int, n_fields: int, parity=1, L=3.0,
-                 rho=None, kind=None, floor_modes: float = 2.0):
+                 rho=None, kind=None, floor_modes: float = 2.0, detector_eps: float = 0.0,
+                 detector_threshold: float = 0.0):
         self.shape = (int(n_fields), int(n_r), int(n_theta), int(n_phi))
-        self._prm = _Params(n_r, n_fields, parity, L, rho, kind, floor_modes)
+        self._prm = _Params(n_r, n_fields, parity, L, rho, kind, floor_modes, detector_eps,
+                            detector_threshold)
+        self.has_hybrid = self._prm.has_hybrid
         h = ctypes.c_void_p()
         lib = _lib.load()
         _lib.check("sphfilt_plan_create",
@@ -149,6 +157,37 @@ class Plan:
         """out = Theta(Phi(x)), the transpose of apply."""
         return self._call("sphfilt_apply_adjoint", x, out, stream)
 
+    def decision_buffers(self, device="cuda"):
+        """Zeroed byte buffers for the hybrid kind's decisions: one per extended
+        theta line [F][n_r][n_phi/2] and one per ring [F][n_r][n_theta]."""
+        import torch
+        F, R, T, P = self.shape
+        return (torch.zeros((F, R, P // 2), dtype=torch.uint8, device=device),
+                torch.zeros((F, R, T), dtype=torch.uint8, device=device))
+
+    def apply_ex(self, x, out=None, adjoint=False, theta_dec=None, phi_dec=None, replay=False,
+                 stream=None):
+        """The filter (adjoint=True: its transpose) with the hybrid decisions
+        recorded into (replay=False) or taken from (replay=True) the buffers."""
+        import torch
+        self._check_tensor(x, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            self._check_tensor(out, "out")
+        F, R, T, P = self.shape
+        for buf, shp, name in ((theta_dec, (F, R, P // 2), "theta_dec"), (phi_dec, (F, R, T), "phi_dec")):
+            if buf is not None and (buf.dtype != torch.uint8 or tuple(buf.shape) != shp or
+                                    buf.device.type != "cuda" or not buf.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous uint8 HIP tensor of shape {shp}")
+        ptr = lambda b: ctypes.c_void_p(b.data_ptr()) if b is not None else None
+        rc = self._lib.sphfilt_apply_ex(self._h, ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), 1 if adjoint else 0,
+                                        ptr(theta_dec), ptr(phi_dec), 1 if replay else 0,
+                                        _stream_handle(x, stream))
+        _lib.check("sphfilt_apply_ex", rc)
+        return out
+
     def apply_theta(self, x, out=None, stream=None):
         return self._call("sphfilt_apply_theta", x, out, stream)
 
@@ -196,7 +235,8 @@ class Batch:
             F, R, T, P = (int(get(p, "n_fields")), int(get(p, "n_r")), int(get(p, "n_theta")),
                           int(get(p, "n_phi")))
             prm = _Params(R, F, get(p, "parity", 1), get(p, "L", 3.0), get(p, "rho"),
-                          get(p, "kind"), get(p, "floor_modes", 2.0))
+                          get(p, "kind"), get(p, "floor_modes", 2.0), get(p, "detector_eps", 0.0),
+                          get(p, "detector_threshold", 0.0))
             self._prms.append(prm)
             self.shapes.append((F, R, T, P))
             descs[i].n_r, descs[i].n_theta, descs[i].n_phi, descs[i].n_fields = R, T, P, F

@@ -45,14 +45,16 @@ def test_version_and_status_strings(L):
 
 
 def _create(L, n_r=4, n_theta=16, n_phi=32, n_fields=2, parity=(1, -1), Lv=(3.0, 3.0),
-            rho=None, kind=None, floor=2.0, null_cut=False, null_parity=False, null_out=False):
+            rho=None, kind=None, floor=2.0, null_cut=False, null_parity=False, null_out=False,
+            det_eps=0.0, det_thr=0.0):
     par = None if null_parity else np.ascontiguousarray(parity, dtype=np.int32)
     Larr = np.ascontiguousarray(Lv, dtype=np.float64)
     rho_a = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
     kind_a = None if kind is None else np.ascontiguousarray(kind, dtype=np.int32)
     cut = L.Cutoff(None if rho_a is None else rho_a.ctypes.data_as(L.c_double_p),
                    Larr.ctypes.data_as(L.c_double_p),
-                   None if kind_a is None else kind_a.ctypes.data_as(L.c_int_p), floor)
+                   None if kind_a is None else kind_a.ctypes.data_as(L.c_int_p), floor, det_eps,
+                   det_thr)
     h = ctypes.c_void_p()
     rc = L.load().sphfilt_plan_create(None if null_out else ctypes.byref(h), n_r, n_theta, n_phi, n_fields,
                                       None if par is None else par.ctypes.data_as(L.c_int_p),
@@ -69,7 +71,8 @@ def _create(L, n_r=4, n_theta=16, n_phi=32, n_fields=2, parity=(1, -1), Lv=(3.0,
     dict(n_phi=33), dict(parity=(1, 0)), dict(parity=(2, 1)), dict(Lv=(3.0, 0.0)),
     dict(Lv=(3.0, -1.0)), dict(Lv=(math.nan, 3.0)), dict(Lv=(math.inf, 3.0)),
     dict(rho=[0.5, 1.5, 0.0, 3.5]), dict(rho=[0.5, 1.5, math.nan, 3.5]),
-    dict(rho=[0.5, -1.5, 2.5, 3.5]), dict(kind=(0, 3)), dict(kind=(-1, 0)),
+    dict(rho=[0.5, -1.5, 2.5, 3.5]), dict(kind=(0, 4)), dict(kind=(-1, 0)),
+    dict(det_eps=-1.0), dict(det_eps=math.nan), dict(det_thr=-0.5), dict(det_thr=math.inf),
     dict(floor=-1.0), dict(floor=math.nan), dict(null_cut=True), dict(null_parity=True),
     dict(null_out=True),
 ])
@@ -145,6 +148,14 @@ def test_workload_stats_gauss_is_never_identity():
     from paper_2305_01537_amd.filter import workload_stats
     st = workload_stats(8, 16, 32, 2, parity=1, L=1000.0, kind=1)
     assert st["theta_shells_active"] == 16 and st["phi_rings_active"] == 2 * 8 * 16
+    # a hybrid field may pick the Gaussian on any line, so it is never skipped either
+    st = workload_stats(8, 16, 32, 2, parity=1, L=1000.0, kind=[3, 0])
+    assert st["theta_shells_active"] == 8 and st["phi_rings_active"] == 8 * 16
+
+
+def test_apply_ex_replay_needs_both_buffers(L):
+    buf = ctypes.c_void_p(0x1000)
+    assert L.load().sphfilt_apply_ex(None, buf, buf, 0, None, None, 1, None) == L.EINVAL
 
 
 def test_workload_stats_validates_like_create():

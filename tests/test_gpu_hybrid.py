@@ -1,0 +1,189 @@
+"""The hybrid filter on the GPU (the paper's automatic exponential/Gaussian switch).
+
+Fields of kind HYBRID pick, per extended theta line and per phi ring, the
+Gaussian filter where Jameson's detector fires and the exponential filter
+otherwise.  Checked against the oracle: the filtered fields, the recorded
+decisions, the frozen-decision (replayed) filter and its transpose, the
+autograd backward, and the batch.  The test fields put steps out of zero on
+chosen lines so that the two real lines sharing one complex transform can
+take different filters.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_01537_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+EXP, GAUSS, SHARP, HYBRID = 0, 1, 2, 3
+
+
+def hybrid_fields(seed=61, shape=(3, 4, 32, 64)):
+    rng = np.random.default_rng(seed)
+    F, R, T, P = shape
+    theta, phi = synth.theta_grid(T), synth.phi_grid(P)
+    x = np.empty(shape)
+    for f in range(F):
+        for i in range(R):
+            x[f, i] = 3.0 + synth.angular_sum(rng, 4, theta, phi, lambda l: 0.2)
+    x[1] *= np.sin(theta)[None, :, None]                 # odd field vanishes on the axis
+    # theta steps: meridian 0 of field 0 / shell 1 drops to zero on the northern half
+    x[0, 1, : T // 2, 0] = 0.0
+    # phi steps: ring 3 of field 0 / shell 2 and ring 5 of field 1 / shell 0
+    x[0, 2, 3, :] = np.where(np.arange(P) < P // 3, 0.0, 2.0)
+    x[1, 0, 5, :] = np.where(np.arange(P) < P // 2, 0.0, 1.0)
+    parity = np.array([1, -1, 1], dtype=np.int32)
+    kind = np.array([HYBRID, HYBRID, EXP], dtype=np.int32)
+    L = np.array([0.6, 0.9, 0.6])
+    return x, parity, kind, L
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def make_plan(x, parity, kind, L):
+    from paper_2305_01537_amd.filter import Plan
+    F, R, T, P = x.shape
+    return Plan(R, T, P, F, parity=parity, L=L, kind=kind)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_hybrid_matches_oracle(torch_gpu):
+    torch = torch_gpu
+    x, parity, kind, L = hybrid_fields()
+    plan = make_plan(x, parity, kind, L)
+    calls = {"apply": oracle.forward, "apply_adjoint": oracle.adjoint,
+             "apply_theta": oracle.theta_pass, "apply_phi": oracle.phi_pass}
+    for name, ref_fn in calls.items():
+        ref = ref_fn(x, parity=parity, L=L, kind=kind)
+        for inplace in (False, True):
+            xd = torch.from_numpy(x).cuda()
+            y = getattr(plan, name)(xd, out=xd if inplace else None)
+            torch.cuda.synchronize()
+            assert rel(y.cpu().numpy(), ref) <= TOL, (name, inplace)
+
+
+def test_hybrid_decisions_match_oracle_and_mix_within_packed_lines(torch_gpu):
+    torch = torch_gpu
+    x, parity, kind, L = hybrid_fields()
+    plan = make_plan(x, parity, kind, L)
+    T = x.shape[2]
+    kw = dict(parity=parity, L=L, kind=kind)
+    # forward: theta decides on the input, phi on the theta-filtered field
+    th, ph = plan.decision_buffers()
+    plan.apply_ex(torch.from_numpy(x).cuda(), theta_dec=th, phi_dec=ph)
+    torch.cuda.synchronize()
+    th, ph = th.cpu().numpy(), ph.cpu().numpy()
+    assert np.array_equal(th, oracle.decisions(x, parity=parity, kind=kind)[0])
+    assert np.array_equal(ph, oracle.decisions(oracle.theta_pass(x, **kw), parity=parity, kind=kind)[1])
+    assert th[0, 1, 0] == 1 and th[0, 1, 16] == 0        # theta pairs 0 and 16 share a transform
+    # adjoint: phi decides on the input, theta on the phi-filtered field
+    tha, pha = plan.decision_buffers()
+    plan.apply_ex(torch.from_numpy(x).cuda(), adjoint=True, theta_dec=tha, phi_dec=pha)
+    torch.cuda.synchronize()
+    tha, pha = tha.cpu().numpy(), pha.cpu().numpy()
+    assert np.array_equal(pha, oracle.decisions(x, parity=parity, kind=kind)[1])
+    assert np.array_equal(tha, oracle.decisions(oracle.phi_pass(x, **kw), parity=parity, kind=kind)[0])
+    assert pha[0, 2, 3] == 1 and pha[0, 2, T - 1 - 3] == 0   # rings 3 and T-4 share a transform
+
+
+def frozen_filter(x, parity, kind, L, th, ph, adjoint=False):
+    """The filter with every hybrid line's kind fixed, composed from the oracle's
+    Gaussian and exponential passes line by line."""
+    kg = np.where(kind == HYBRID, GAUSS, kind)
+    ke = np.where(kind == HYBRID, EXP, kind)
+    mth = np.concatenate([th, th], axis=-1)[:, :, None, :].astype(bool)     # both meridians
+    mph = ph[:, :, :, None].astype(bool)
+
+    def theta(z):
+        return np.where(mth, oracle.theta_pass(z, parity=parity, L=L, kind=kg),
+                        oracle.theta_pass(z, parity=parity, L=L, kind=ke))
+
+    def phi(z):
+        return np.where(mph, oracle.phi_pass(z, parity=parity, L=L, kind=kg),
+                        oracle.phi_pass(z, parity=parity, L=L, kind=ke))
+    return theta(phi(x)) if adjoint else phi(theta(x))
+
+
+def test_hybrid_replay_is_the_frozen_filter_and_its_transpose(torch_gpu):
+    torch = torch_gpu
+    x, parity, kind, L = hybrid_fields()
+    plan = make_plan(x, parity, kind, L)
+    th, ph = plan.decision_buffers()
+    plan.apply_ex(torch.from_numpy(x).cuda(), theta_dec=th, phi_dec=ph)
+    rng = np.random.default_rng(62)
+    y = rng.standard_normal(x.shape)
+    z = rng.standard_normal(x.shape)
+    fy = plan.apply_ex(torch.from_numpy(y).cuda(), theta_dec=th, phi_dec=ph, replay=True)
+    ftz = plan.apply_ex(torch.from_numpy(z).cuda(), adjoint=True, theta_dec=th, phi_dec=ph, replay=True)
+    torch.cuda.synchronize()
+    thn, phn = th.cpu().numpy(), ph.cpu().numpy()
+    assert rel(fy.cpu().numpy(), frozen_filter(y, parity, kind, L, thn, phn)) <= TOL
+    assert rel(ftz.cpu().numpy(), frozen_filter(z, parity, kind, L, thn, phn, adjoint=True)) <= TOL
+    fyn, ftzn = fy.cpu().numpy(), ftz.cpu().numpy()
+    lhs = np.sum(fyn.astype(np.longdouble) * z.astype(np.longdouble))
+    rhs = np.sum(y.astype(np.longdouble) * ftzn.astype(np.longdouble))
+    assert float(abs(lhs - rhs)) / (np.linalg.norm(fyn) * np.linalg.norm(z)) <= 1e-13
+
+
+def test_hybrid_autograd_uses_the_recorded_decisions(torch_gpu):
+    torch = torch_gpu
+    from paper_2305_01537_amd.autograd import sph_filter
+    x, parity, kind, L = hybrid_fields()
+    plan = make_plan(x, parity, kind, L)
+    xd = torch.from_numpy(x).cuda().requires_grad_(True)
+    g = torch.from_numpy(np.random.default_rng(63).standard_normal(x.shape)).cuda()
+    y = sph_filter(xd, plan)
+    y.backward(g)
+    th, ph = plan.decision_buffers()
+    plan.apply_ex(torch.from_numpy(x).cuda(), theta_dec=th, phi_dec=ph)
+    ref = plan.apply_ex(g, adjoint=True, theta_dec=th, phi_dec=ph, replay=True)
+    torch.cuda.synchronize()
+    assert torch.equal(xd.grad, ref)
+    # small perturbations leave the decisions alone: central differences agree
+    h = 1e-6
+    rng = np.random.default_rng(64)
+    w = torch.from_numpy(rng.standard_normal(x.shape)).cuda()
+    with torch.no_grad():
+        for k in rng.choice(x.size, 12, replace=False):
+            xp = torch.from_numpy(x).cuda().view(-1)
+            xm = xp.clone()
+            xp[k] += h
+            xm[k] -= h
+            fd = float(((plan.apply(xp.view(x.shape)) - plan.apply(xm.view(x.shape))) * w).sum()) / (2 * h)
+            ad = float(plan.apply_ex(w, adjoint=True, theta_dec=th, phi_dec=ph, replay=True).view(-1)[k])
+            assert abs(fd - ad) <= 1e-6 * max(1.0, abs(ad))
+
+
+def test_hybrid_batch_equals_plans(torch_gpu):
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Batch
+    pats = []
+    for seed, shape in ((61, (3, 4, 32, 64)), (65, (3, 3, 16, 32)), (66, (3, 3, 64, 128))):
+        x, parity, kind, L = hybrid_fields(seed, shape)
+        pats.append(dict(n_fields=shape[0], n_r=shape[1], n_theta=shape[2], n_phi=shape[3],
+                         parity=parity, kind=kind, L=L, x=x))
+    refs = []
+    for p in pats:
+        plan = make_plan(p["x"], p["parity"], p["kind"], p["L"])
+        refs.append(plan.apply(torch.from_numpy(p["x"]).cuda()).cpu().numpy())
+    batch = Batch(pats)
+    for split in (0, 1):
+        for wpc in (-1, 1):
+            batch.set_schedule(split, wpc)
+            ys = batch.apply([torch.from_numpy(p["x"]).cuda() for p in pats])
+            torch.cuda.synchronize()
+            assert batch.status() == 0
+            for y, r in zip(ys, refs):
+                ok = bool(np.array_equal(y.cpu().numpy(), r))
+                assert ok, (split, wpc)
