@@ -161,9 +161,11 @@ __global__ __launch_bounds__(256) void batch_kernel_oneshot(BatchArgs a)
 // Persistent form: a fixed grid; each workgroup takes tickets until the list
 // is exhausted.  The lane index is re-read through an opaque move every item
 // so that per-lane index math is recomputed rather than kept live across
-// items (it would otherwise not fit in 256 registers).
+// items (it would otherwise not fit in 256 registers).  The hybrid form, with
+// the detector and the mixed-pair mask, needs more than 256 registers; it runs
+// one wave per SIMD instead of spilling to scratch.
 template <bool HYB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel_persistent(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HYB ? 1 : 2))) void batch_kernel_persistent(
     BatchArgs a)
 {
     __shared__ double lds[kBatchLds];
