@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--patches-only", action="store_true",
                     help="time only the 64-patch batch and print its figures as JSON "
                          "(for profiling the batch kernel)")
+    ap.add_argument("--grmhd-only", action="store_true",
+                    help="time only the grmhd grid, fused and two-pass, and print its figures "
+                         "as JSON (for profiling the fused shell kernel)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -169,6 +172,37 @@ def bench_patches(torch, steps, stream):
     return out
 
 
+def bench_grmhd(torch, steps, stream):
+    """The grmhd grid (24 x 128 x 64 x 128, 201 MB, paper cutoff): shells fit in
+    LDS, so the plan fuses the theta-filtered shells; timed fused and as two
+    passes, forward and adjoint in place.  Five rotated buffers (1 GB) keep the
+    data out of the 256 MB last-level cache."""
+    from paper_2305_01537_amd import synth
+    from paper_2305_01537_amd.filter import Plan
+    w = synth.workload("grmhd")
+    F, R, T, P = w.shape
+    plan = Plan(R, T, P, F, parity=w.parity, L=w.L, rho=w.rho)
+    st = plan.stats()
+    x0 = torch.from_numpy(w.x).cuda()
+    bufs = [x0] + [x0.clone() for _ in range(4)]
+    out = {"workload": f"grmhd: {F} x {R} x {T} x {P}, cal-L={float(w.L[0])}",
+           "points": st["n_points"], "shells_fused": st["shells_fused"],
+           "bytes_two_pass": st["bytes_forward_inplace"], "bytes_fused": st["bytes_fused_inplace"]}
+    for fused in (True, False):
+        plan.set_fused(fused)
+        tag = "fused" if fused else "two_pass"
+        ms_f = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 3, stream)
+        ms_a = time_loop(torch, lambda b: plan.apply_adjoint(b, out=b), bufs, steps, 3, stream)
+        nbytes = st["bytes_fused_inplace"] if fused else st["bytes_forward_inplace"]
+        out[tag] = {"forward_ms": ms_f, "adjoint_ms": ms_a,
+                    "points_per_s": st["n_points"] / (ms_f * 1e-3),
+                    "GBps": nbytes / (ms_f * 1e-3) / 1e9}
+    out["fused_speedup"] = out["two_pass"]["forward_ms"] / out["fused"]["forward_ms"]
+    plan.close()
+    del bufs, x0
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -187,6 +221,9 @@ def main():
     t_start = time.perf_counter()
     if args.patches_only:
         print(json.dumps({"patches": bench_patches(torch, args.steps, stream)}), flush=True)
+        return 0
+    if args.grmhd_only:
+        print(json.dumps({"grmhd": bench_grmhd(torch, args.steps, stream)}), flush=True)
         return 0
 
     log("generating the share workload (24 x 256 x 128 x 256, FP64)")
@@ -258,6 +295,9 @@ def main():
         }
         log(f"dense: {extra['dense']}")
         dplan.close()
+        log("timing the grmhd grid (fused shells)")
+        extra["grmhd"] = bench_grmhd(torch, max(10, args.steps // 2), stream)
+        log(f"grmhd: {extra['grmhd']}")
         log("timing the 64-patch batch")
         extra["patches"] = bench_patches(torch, max(10, args.steps // 2), stream)
         log(f"patches: {extra['patches']}")

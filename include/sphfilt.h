@@ -99,6 +99,12 @@ typedef struct {
  *                        written per point of every line a pass must touch.
  *                        In place, identity lines are skipped; out of place,
  *                        the first pass also copies its identity lines.
+ *   shells_fused         shells a plan sends through the fused shell kernel
+ *                        (see sphfilt_plan_set_fused); 0 if the grid does not
+ *                        allow it
+ *   bytes_fused_inplace  algorithmic bytes of one in-place call (forward or
+ *                        adjoint) with those shells fused: 16 B per point of a
+ *                        fused shell, plus the two-pass figure of the rest
  */
 typedef struct {
     long long n_points;
@@ -107,6 +113,7 @@ typedef struct {
     long long phi_rings_total, phi_rings_active;
     long long bytes_forward_inplace, bytes_forward_outofplace;
     long long bytes_adjoint_inplace, bytes_adjoint_outofplace;
+    long long shells_fused, bytes_fused_inplace;
 } sphfilt_stats;
 
 /*
@@ -195,6 +202,27 @@ int sphfilt_workload_stats(int n_r, int n_theta, int n_phi, int n_fields, const 
  */
 int sphfilt_plan_set_schedule(sphfilt_plan plan, int theta_cols, int phi_lines);
 int sphfilt_plan_get_schedule(sphfilt_plan plan, int *theta_cols, int *phi_lines);
+
+/*
+ * Fused shells.  On grids with n_phi = 2 * n_theta and n_phi <= 128 a whole
+ * shell (field, radius) fits in one workgroup's LDS.  A shell whose every
+ * theta line and every ring is filtered (no identity line) then goes through
+ * one kernel that loads it once, runs both passes in LDS and registers, and
+ * stores it once: one HBM round trip instead of two (the passes are applied
+ * in the order of the call, so the operator is unchanged).  The other shells
+ * take the two-pass path (on these grids only ring pairs are left: a shell
+ * the theta pass filters has all its rings filtered, since m_max <= l_max),
+ * in the same launch.  Results equal those of the two-pass path up to
+ * rounding (the same line transforms, with multiply-adds contracted
+ * differently by the compiler).
+ *   enable  1 (the default): fuse where possible; 0: always two passes.
+ * set_fused returns SPHFILT_EINVAL for other values; it is not thread-safe
+ * against concurrent apply calls on the same plan.  get_fused reports the
+ * setting and the number of shells fused when it is on (NULL outputs are
+ * skipped).
+ */
+int sphfilt_plan_set_fused(sphfilt_plan plan, int enable);
+int sphfilt_plan_get_fused(sphfilt_plan plan, int *enable, int *shells_fused);
 
 /* ======================================================================
  * Batched filter: many uneven spherical patches in one launch.

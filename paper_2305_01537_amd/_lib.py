@@ -26,7 +26,8 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_longlong) for n in (
         "n_points", "theta_shells_total", "theta_shells_active", "theta_lines_total",
         "theta_lines_active", "phi_rings_total", "phi_rings_active", "bytes_forward_inplace",
-        "bytes_forward_outofplace", "bytes_adjoint_inplace", "bytes_adjoint_outofplace")]
+        "bytes_forward_outofplace", "bytes_adjoint_inplace", "bytes_adjoint_outofplace",
+        "shells_fused", "bytes_fused_inplace")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -53,6 +54,8 @@ SIGNATURES = {
                                               c_int_p, ctypes.POINTER(Cutoff), ctypes.POINTER(Stats)]),
     "sphfilt_plan_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "sphfilt_plan_get_schedule": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
+    "sphfilt_plan_set_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sphfilt_plan_get_fused": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
     "sphfilt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                             ctypes.POINTER(PatchDesc), ctypes.c_char_p]),
     "sphfilt_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),

@@ -661,6 +661,9 @@ int sphfilt_batch_stats(sphfilt_batch batch, sphfilt_stats *out)
         const long long *src = (const long long *)&s;
         for (size_t i = 0; i < sizeof(s) / sizeof(long long); ++i) dst[i] += src[i];
     }
+    // the batch runs every patch in two passes
+    out->shells_fused = 0;
+    out->bytes_fused_inplace = 0;
     return SPHFILT_OK;
 }
 

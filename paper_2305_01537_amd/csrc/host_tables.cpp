@@ -93,8 +93,10 @@ int validate(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
 void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
                  const sphfilt_cutoff *cut, HostTables *h)
 {
-    std::vector<ThetaItem> ta, ti;
-    std::vector<PhiItem> pa, pi;
+    const bool fusable = shell_fusable(n_theta, n_phi);
+    std::vector<ThetaItem> tf, ta, ti;     // fused, other active, identity shells
+    std::vector<PhiItem> pa, pi, ra, ri;   // all rings; rings of unfused shells
+    std::vector<PhiItem> rings;
     for (int f = 0; f < n_fields; ++f) {
         const int kind = cut->kind ? cut->kind[f] : SPHFILT_EXP;
         const int base_flags = kind | (parity[f] < 0 ? kFlagOddParity : 0);
@@ -107,23 +109,39 @@ void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parit
             const bool may_skip = kind == SPHFILT_EXP || kind == SPHFILT_SHARP;
             const bool ident = may_skip && c >= (double)n_theta;
             const ThetaItem t{f * n_r + i, base_flags | (ident ? kFlagIdentity : 0), c};
-            (ident ? ti : ta).push_back(t);
+            rings.clear();
+            bool all_rings = true;
             for (int j = 0; j < n_theta / 2; ++j) {
                 const double s = std::sin(((double)j + 0.5) * kPi / (double)n_theta);
                 double m = 2.0 * rho * s * L;
                 if (!(m > cut->floor_modes)) m = cut->floor_modes;
                 const bool pid = may_skip && m >= (double)(n_phi / 2);
+                all_rings = all_rings && !pid;
                 const PhiItem p{(f * n_r + i) * n_theta + j, base_flags | (pid ? kFlagIdentity : 0), m};
+                rings.push_back(p);
                 (pid ? pi : pa).push_back(p);
+            }
+            const bool fuse = fusable && !ident && all_rings;
+            if (fuse) {
+                tf.push_back(t);
+                for (const PhiItem &p : rings) h->fused_c.push_back(p.c);
+            } else {
+                (ident ? ti : ta).push_back(t);
+                for (const PhiItem &p : rings) ((p.flags & kFlagIdentity) ? ri : ra).push_back(p);
             }
         }
     }
-    h->theta_active = (int)ta.size();
+    h->n_fused = (int)tf.size();
+    h->theta_active = (int)(tf.size() + ta.size());
     h->phi_active = (int)pa.size();
-    h->theta = std::move(ta);
+    h->theta = std::move(tf);
+    h->theta.insert(h->theta.end(), ta.begin(), ta.end());
     h->theta.insert(h->theta.end(), ti.begin(), ti.end());
     h->phi = std::move(pa);
     h->phi.insert(h->phi.end(), pi.begin(), pi.end());
+    h->phi_rest_active = (int)ra.size();
+    h->phi_rest = std::move(ra);
+    h->phi_rest.insert(h->phi_rest.end(), ri.begin(), ri.end());
 }
 
 HybridArgs hybrid_args(const sphfilt_cutoff *cut, int n_fields)
@@ -152,6 +170,10 @@ void fill_stats(int n_r, int n_theta, int n_phi, int n_fields, const HostTables 
     s->bytes_forward_outofplace = 16 * (s->n_points + ph_act);
     s->bytes_adjoint_inplace = 16 * (ph_act + th_act);
     s->bytes_adjoint_outofplace = 16 * (s->n_points + th_act);
+    s->shells_fused = h.n_fused;
+    const long long fused_pts = (long long)h.n_fused * shell_pts;
+    const long long th_rest = (long long)(h.theta_active - h.n_fused) * shell_pts;
+    s->bytes_fused_inplace = 16 * (fused_pts + th_rest + 2LL * h.phi_rest_active * n_phi);
 }
 
 }  // namespace sphfilt

@@ -9,11 +9,19 @@ namespace sphfilt {
 
 // Item lists of one (n_r x n_theta x n_phi, n_fields) grid.  Items whose mask
 // is 1 on every mode come after the others (active prefix, then identity).
+// Fused schedule (shell_fusable grids only): theta items [0, n_fused) are the
+// shells whose every theta line and ring is filtered, fused_c their ring-pair
+// cutoffs (n_theta/2 per shell, j ascending); phi_rest holds the phi items of
+// all other shells (active prefix of phi_rest_active items, then identity).
 struct HostTables {
     std::vector<ThetaItem> theta;
     std::vector<PhiItem> phi;
     int theta_active = 0;
     int phi_active = 0;
+    int n_fused = 0;
+    std::vector<double> fused_c;
+    std::vector<PhiItem> phi_rest;
+    int phi_rest_active = 0;
 };
 
 bool fault(const char *what);

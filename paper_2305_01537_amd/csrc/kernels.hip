@@ -42,6 +42,36 @@ __global__ __launch_bounds__(LINES * Split<N>::N2) SPHFILT_OCCUPANCY void phi_ke
                         lds, etab, flags, h, threadIdx.x);
 }
 
+// Fused shells and, in the same grid, ring pairs of the other shells: blocks
+// [0, shell_groups) run shell_block on `shells`, the rest run phi_block
+// (256/N2 ring pairs each) on `rings`.  The two sets touch different shells,
+// so one launch lets the ring-pair workgroups stream while the shell
+// workgroups load, filter and store their shells.
+template <int N, bool ADJ, bool HYB>
+__global__ __launch_bounds__(256) void shell_phi_kernel(
+    const double *in, double *out, const ThetaItem *__restrict__ shells,
+    const double *__restrict__ ring_c, int n_shells, int shell_groups,
+    const PhiItem *__restrict__ rings, int n_rings, const Twiddle *__restrict__ tw,
+    const double *__restrict__ eneg, HybridArgs ht, HybridArgs hp)
+{
+    using S = ShellShape<N>;
+    constexpr int LINES = 256 / Split<N>::N2;
+    static_assert(S::lds >= LINES * line_lds<Split<N>::N1, Split<N>::N2>(), "ring-pair scratch");
+    __shared__ double lds[S::lds];
+    __shared__ double etab[N / 2 + 1];
+    __shared__ int flags[LINES];
+    if ((int)blockIdx.x < shell_groups) {
+        const int first = blockIdx.x * S::shells;
+        shell_block<N, ADJ, HYB>(in, out, shells + first, ring_c + (size_t)first * S::lines,
+                                 min(S::shells, n_shells - first), tw, eneg, lds, etab, flags, ht,
+                                 hp, threadIdx.x);
+    } else {
+        const int first = ((int)blockIdx.x - shell_groups) * LINES;
+        phi_block<N, LINES, HYB>(in, out, rings + first, min(LINES, n_rings - first), N / 2, tw,
+                                 eneg, lds, etab, flags, hp, threadIdx.x);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launch shapes
 // ---------------------------------------------------------------------------
@@ -180,6 +210,61 @@ hipError_t launch_phi(int n_line, int lines, const double *in, double *out, cons
     case 64: return phi_lines<64>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 128: return phi_lines<128>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 256: return phi_lines<256>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool shell_fusable(int n_theta, int n_phi)
+{
+    return n_phi == 2 * n_theta && (n_phi == 32 || n_phi == 64 || n_phi == 128);
+}
+
+int shells_per_group(int n_phi)
+{
+    switch (n_phi) {
+    case 32: return ShellShape<32>::shells;
+    case 64: return ShellShape<64>::shells;
+    case 128: return ShellShape<128>::shells;
+    default: return 0;
+    }
+}
+
+
+template <int N>
+static hipError_t shell_phi_go(bool adjoint, const double *in, double *out,
+                               const ThetaItem *shells, const double *ring_c, int n_shells,
+                               const PhiItem *rings, int n_rings, const Twiddle *tw,
+                               const double *eneg, const HybridArgs &ht, const HybridArgs &hp,
+                               hipStream_t s)
+{
+    constexpr int LINES = 256 / Split<N>::N2;
+    const int groups = (n_shells + ShellShape<N>::shells - 1) / ShellShape<N>::shells;
+    const dim3 grid((unsigned)(groups + (n_rings + LINES - 1) / LINES)), block(256);
+    const bool hyb = ht.present != 0;
+#define SPHFILT_SHELL_PHI(A, H)                                                                    \
+    shell_phi_kernel<N, A, H><<<grid, block, 0, s>>>(in, out, shells, ring_c, n_shells, groups,    \
+                                                     rings, n_rings, tw, eneg, ht, hp)
+    if (adjoint) {
+        if (hyb) SPHFILT_SHELL_PHI(true, true); else SPHFILT_SHELL_PHI(true, false);
+    } else {
+        if (hyb) SPHFILT_SHELL_PHI(false, true); else SPHFILT_SHELL_PHI(false, false);
+    }
+#undef SPHFILT_SHELL_PHI
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_phi(bool adjoint, int n_theta, int n_phi, const double *in, double *out,
+                            const ThetaItem *shells, const double *ring_c, int n_shells,
+                            const PhiItem *rings, int n_rings, const Twiddle *tw,
+                            const double *eneg, const HybridArgs &ht, const HybridArgs &hp,
+                            hipStream_t s)
+{
+    if (n_shells < 0 || n_rings < 0 || !shell_fusable(n_theta, n_phi)) return hipErrorInvalidValue;
+    if (n_shells + n_rings == 0) return hipSuccess;
+    switch (n_phi) {
+    case 32: return shell_phi_go<32>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
+    case 64: return shell_phi_go<64>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
+    case 128: return shell_phi_go<128>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -528,3 +528,179 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
 }
 
 }  // namespace sphfilt
+
+namespace sphfilt {
+
+// ---------------------------------------------------------------------------
+// Fused shell worker: both passes of a shell with one HBM round trip.
+// For n_phi = 2 n_theta = N a theta line and a phi ring have the same length
+// N, and a shell has as many complex theta lines (meridian pairs k and
+// k + N/4) as complex phi lines (ring pairs j and n_theta-1-j): N/4.  A
+// 256-lane workgroup takes `shells` whole shells: it stages them in LDS with
+// contiguous loads, filters them line by line in the theta layout, writes the
+// result back into the staged shells, filters them in the phi layout and
+// stores them with contiguous stores (the adjoint order runs the phi pass
+// first).  Lines are packed and filtered exactly as by theta_block (with
+// cols = n_phi/4) and phi_block, so the result is bitwise that of the two
+// passes.  The line filter's LDS scratch reuses the staging memory.
+// ---------------------------------------------------------------------------
+template <int N> struct ShellShape {
+    static constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+    static constexpr int lines = N / 4;                  // complex lines per shell and pass
+    static constexpr int lanes = lines * N2;             // lanes per shell
+    static constexpr int shells = 256 / lanes;           // shells per workgroup
+    static constexpr int row = N + (N2 == 4 ? 4 : 8);    // padded row stride, doubles
+    static constexpr int stride = (N / 2) * row + 16;    // doubles per staged shell
+    static constexpr int lds = shells * stride;
+    static_assert(lanes % N == 0, "a shell's lanes cover whole rows");
+    static_assert(lds >= (256 / N2) * line_lds<N1, N2>(), "scratch fits in the staging area");
+};
+
+// Staging: lane l of a shell's lanes moves elements e = k * lanes + l,
+// k < 2 N1, of the shell (row e / N, column e % N).
+template <int N, bool LOAD>
+__device__ __forceinline__ void shell_stage(const double *in, double *out, double *sb, cplx (&v)[Split<N>::N1],
+                                            size_t base, bool valid, int l)
+{
+    using S = ShellShape<N>;
+    constexpr int R = S::lanes / N;                      // rows per k step
+    const int r0 = l / N, col = l % N;
+    static_for<0, 2 * S::N1>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        double &x = (k & 1) ? v[k / 2].im : v[k / 2].re;
+        double *s = sb + (k * R + r0) * S::row + col;
+        if constexpr (LOAD) {
+            x = valid ? ld_stream(in + base + (size_t)k * S::lanes + l) : 0.0;
+            *s = x;
+        } else {
+            x = *s;
+            if (valid) st_stream<true>(out + base + (size_t)k * S::lanes + l, x);
+        }
+    });
+}
+
+// theta layout: lane (p, t), p = lane % C fastest; line p packs meridian
+// pairs kr = p % lines and ki = kr + lines of staged shell p / lines.
+template <int N, bool WRITE>
+__device__ __forceinline__ void shell_theta_io(cplx (&v)[Split<N>::N1], double *sb, int t, int kr, double s)
+{
+    using S = ShellShape<N>;
+    constexpr int N1 = S::N1, N2 = S::N2, half = N / 2;
+    const int ki = kr + S::lines;
+    static_for<0, N1>([&](auto nn) {
+        constexpr int n1 = decltype(nn)::value;
+        if constexpr (n1 < N1 / 2) {
+            double *r = sb + (N2 * n1 + t) * S::row;
+            if constexpr (WRITE) { r[kr] = v[n1].re; r[ki] = v[n1].im; }
+            else v[n1] = cplx{r[kr], r[ki]};
+        } else {
+            double *r = sb + (N - 1 - N2 * n1 - t) * S::row + half;
+            if constexpr (WRITE) { r[kr] = s * v[n1].re; r[ki] = s * v[n1].im; }
+            else v[n1] = cplx{s * r[kr], s * r[ki]};
+        }
+    });
+}
+
+// phi layout: lane (p, t), t = lane % N2 fastest; line p packs rings j and
+// n_theta-1-j, j = p % lines, of staged shell p / lines.
+template <int N, bool WRITE>
+__device__ __forceinline__ void shell_phi_io(cplx (&v)[Split<N>::N1], double *sb, int t, int j)
+{
+    using S = ShellShape<N>;
+    constexpr int N1 = S::N1, N2 = S::N2;
+    double *ra = sb + j * S::row + t;
+    double *rb = sb + (N / 2 - 1 - j) * S::row + t;
+    static_for<0, N1>([&](auto nn) {
+        constexpr int n1 = decltype(nn)::value;
+        if constexpr (WRITE) { ra[N2 * n1] = v[n1].re; rb[N2 * n1] = v[n1].im; }
+        else v[n1] = cplx{ra[N2 * n1], rb[N2 * n1]};
+    });
+}
+
+// items: the workgroup's shells (n_valid of them); ring_c: their phi cutoffs,
+// lines per shell.  ht / hp: hybrid arguments of the theta and phi passes.
+template <int N, bool ADJ, bool HYB>
+__device__ __forceinline__ void shell_block(const double *in, double *out,
+                                            const ThetaItem *__restrict__ items,
+                                            const double *__restrict__ ring_c, int n_valid,
+                                            const Twiddle *__restrict__ tw,
+                                            const double *__restrict__ eneg, double *lds,
+                                            double *etab, int *flags, const HybridArgs &ht,
+                                            const HybridArgs &hp, int lane)
+{
+    using S = ShellShape<N>;
+    constexpr int N1 = S::N1, N2 = S::N2, C = 256 / N2;
+    constexpr size_t shell_pts = (size_t)N * N / 2;
+    stage_exp_table<N>(etab, eneg, lane);
+
+    // staging
+    const int us = lane / S::lanes;
+    const bool valid_s = us < n_valid;
+    const size_t base_s = valid_s ? (size_t)items[us].shell * shell_pts : 0;
+    cplx v[N1];
+    shell_stage<N, true>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
+    __syncthreads();
+
+    // theta layout
+    const int pt = lane % C, tt = lane / C, ut = pt / S::lines, kr = pt % S::lines;
+    const bool valid_t = ut < n_valid;
+    const ThetaItem it = valid_t ? items[ut] : ThetaItem{0, 0, 0.0};
+    const double sgn = (it.flags & kFlagOddParity) ? -1.0 : 1.0;
+    double *sb_t = lds + ut * S::stride;
+    // phi layout
+    const int tp = lane % N2, pp = lane / N2, up = pp / S::lines, j = pp % S::lines;
+    const bool valid_p = up < n_valid;
+    const int shell_p = valid_p ? items[up].shell : 0;
+    const int kind_p = valid_p ? (items[up].flags & kKindMask) : 0;
+    const double c_p = valid_p ? ring_c[up * S::lines + j] : INFINITY;
+    double *sb_p = lds + up * S::stride;
+
+    auto theta_filter = [&]() {
+        double *L = lds + pt * line_lds<N1, N2>();
+        int ka = it.flags & kKindMask, kb = ka;
+        bool mixed = false;
+        if constexpr (HYB) {
+            const size_t dline = (size_t)it.shell * (size_t)(N / 2);
+            hybrid_kinds<N1, N2>(v, tt, L, flags + pt, valid_t, ka, dline + kr,
+                                 dline + kr + S::lines, ht, &ka, &kb, &mixed);
+        }
+        filter_line<N1, N2, HYB>(v, tt, ka, kb, mixed, valid_t ? it.c : INFINITY, L, tw, etab);
+    };
+    auto phi_filter = [&]() {
+        double *L = lds + pp * line_lds<N1, N2>();
+        int ka = kind_p, kb = ka;
+        bool mixed = false;
+        if constexpr (HYB) {
+            const size_t ring = (size_t)shell_p * (size_t)(N / 2) + j;
+            hybrid_kinds<N1, N2>(v, tp, L, flags + pp, valid_p, ka, ring,
+                                 ring + (size_t)(N / 2 - 1 - 2 * j), hp, &ka, &kb, &mixed);
+        }
+        filter_line<N1, N2, HYB>(v, tp, ka, kb, mixed, c_p, L, tw, etab);
+    };
+
+    if constexpr (!ADJ) {
+        shell_theta_io<N, false>(v, sb_t, tt, kr, sgn);
+        __syncthreads();
+        theta_filter();
+        shell_theta_io<N, true>(v, sb_t, tt, kr, sgn);
+        __syncthreads();
+        shell_phi_io<N, false>(v, sb_p, tp, j);
+        __syncthreads();
+        phi_filter();
+        shell_phi_io<N, true>(v, sb_p, tp, j);
+    } else {
+        shell_phi_io<N, false>(v, sb_p, tp, j);
+        __syncthreads();
+        phi_filter();
+        shell_phi_io<N, true>(v, sb_p, tp, j);
+        __syncthreads();
+        shell_theta_io<N, false>(v, sb_t, tt, kr, sgn);
+        __syncthreads();
+        theta_filter();
+        shell_theta_io<N, true>(v, sb_t, tt, kr, sgn);
+    }
+    __syncthreads();
+    shell_stage<N, false>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
+}
+
+}  // namespace sphfilt

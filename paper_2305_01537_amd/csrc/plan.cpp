@@ -10,6 +10,9 @@
 // sharp filters) are sorted after the others: an in-place call launches over
 // the non-identity prefix only, an out-of-place call over all items and the
 // identity ones are copied.
+// On grids whose shells fit in LDS (n_phi = 2 n_theta <= 128), shells with no
+// identity line are run by the fused shell kernel (both passes, one HBM round
+// trip), in one launch with the ring pairs of the remaining shells.
 #include "../../include/sphfilt.h"
 #include "host_tables.h"
 #include "sphfilt_internal.h"
@@ -33,6 +36,8 @@ struct DeviceTables {
     Twiddle *tw_theta = nullptr;
     Twiddle *tw_phi = nullptr;
     double *eneg = nullptr;
+    double *fused_c = nullptr;
+    PhiItem *phi_rest = nullptr;
 };
 
 }  // namespace
@@ -43,6 +48,7 @@ struct sphfilt_plan_s {
     HostTables host;
     DeviceTables dev;
     int theta_cols, phi_lines;
+    int fused;              // fuse shells where the grid allows it
     HybridArgs hybrid;      // detector parameters; dec / replay set per call
 };
 
@@ -55,6 +61,8 @@ void free_device(DeviceTables *d)
     if (d->tw_theta) (void)hipFree(d->tw_theta);
     if (d->tw_phi) (void)hipFree(d->tw_phi);
     if (d->eneg) (void)hipFree(d->eneg);
+    if (d->fused_c) (void)hipFree(d->fused_c);
+    if (d->phi_rest) (void)hipFree(d->phi_rest);
     *d = DeviceTables{};
 }
 
@@ -96,6 +104,29 @@ int check_call(sphfilt_plan p, const double *in, double *out)
     return SPHFILT_OK;
 }
 
+// Fused shells and the phi pass of the other shells' ring pairs, in one
+// launch.  On a fusable grid (n_phi = 2 n_theta) a shell that the theta pass
+// filters has every ring filtered too (m_max <= l_max < n_theta = n_phi / 2,
+// also in floating point: rounding is monotone), so all of them are fused and
+// the theta pass has nothing left: the other shells only need their rings
+// (copied out of place when identity).  Returns SPHFILT_EUNSUPPORTED if some
+// theta-filtered shell was not fused; the caller then runs two passes.
+int apply_fused(sphfilt_plan p, bool adjoint, const double *in, double *out, const Decisions &d,
+                hipStream_t s)
+{
+    const HostTables &t = p->host;
+    if (t.theta_active != t.n_fused) return SPHFILT_EUNSUPPORTED;
+    HybridArgs ht = p->hybrid, hp = p->hybrid;
+    ht.replay = hp.replay = d.replay;
+    ht.dec = d.theta;
+    hp.dec = d.phi;
+    const int n_rings = in == out ? t.phi_rest_active : (int)t.phi_rest.size();
+    const hipError_t e = launch_shell_phi(adjoint, p->n_theta, p->n_phi, in, out, p->dev.theta,
+                                          p->dev.fused_c, t.n_fused, p->dev.phi_rest, n_rings,
+                                          p->dev.tw_phi, p->dev.eneg, ht, hp, s);
+    return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
+}
+
 // Two passes in the given order.  Out of place, the first pass runs over all
 // items (copying identity lines) and the second works in place on `out`.
 int apply_two(sphfilt_plan p, Pass first, Pass second, const double *in, double *out,
@@ -106,6 +137,10 @@ int apply_two(sphfilt_plan p, Pass first, Pass second, const double *in, double 
     DeviceGuard g(p->device);
     if (!g.ok) return SPHFILT_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
+    if (p->fused && p->host.n_fused > 0) {
+        rc = apply_fused(p, first == Pass::Phi, in, out, d, s);
+        if (rc != SPHFILT_EUNSUPPORTED) return rc;
+    }
     const bool inplace = in == out;
     rc = run_pass(p, first, in, out, !inplace, d, s);
     if (rc) return rc;
@@ -158,6 +193,7 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
     p->theta_cols = default_theta_cols(2 * n_theta, n_phi);
     p->hybrid = hybrid_args(cut, n_fields);
     p->phi_lines = default_phi_lines(n_phi);
+    p->fused = 1;
     try {
         build_items(n_r, n_theta, n_phi, n_fields, parity, cut, &p->host);
         if (hipGetDevice(&p->device) != hipSuccess) rc = SPHFILT_EDEVICE;
@@ -166,6 +202,8 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
         if (!rc) rc = upload(&p->dev.tw_theta, twiddles(2 * n_theta));
         if (!rc) rc = upload(&p->dev.tw_phi, twiddles(n_phi));
         if (!rc) rc = upload(&p->dev.eneg, exp_table());
+        if (!rc) rc = upload(&p->dev.fused_c, p->host.fused_c);
+        if (!rc) rc = upload(&p->dev.phi_rest, p->host.phi_rest);
     } catch (const std::bad_alloc &) {
         rc = SPHFILT_ENOMEM;
     }
@@ -242,6 +280,21 @@ int sphfilt_plan_get_schedule(sphfilt_plan plan, int *theta_cols, int *phi_lines
     if (!plan) return SPHFILT_EINVAL;
     if (theta_cols) *theta_cols = plan->theta_cols;
     if (phi_lines) *phi_lines = plan->phi_lines;
+    return SPHFILT_OK;
+}
+
+int sphfilt_plan_set_fused(sphfilt_plan plan, int enable)
+{
+    if (!plan || (enable != 0 && enable != 1)) return SPHFILT_EINVAL;
+    plan->fused = enable;
+    return SPHFILT_OK;
+}
+
+int sphfilt_plan_get_fused(sphfilt_plan plan, int *enable, int *shells_fused)
+{
+    if (!plan) return SPHFILT_EINVAL;
+    if (enable) *enable = plan->fused;
+    if (shells_fused) *shells_fused = plan->fused ? plan->host.n_fused : 0;
     return SPHFILT_OK;
 }
 

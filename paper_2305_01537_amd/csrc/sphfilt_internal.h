@@ -60,6 +60,22 @@ hipError_t launch_phi(int n_line, int lines, const double *in, double *out, cons
                       int n_items, int n_theta, const Twiddle *tw, const double *eneg,
                       const HybridArgs &h, hipStream_t stream);
 
+// Fused shells: both passes of n_shells shells (every line of which is
+// filtered), in the order given by `adjoint`, and in the same launch the phi
+// pass of n_rings ring pairs of other shells (256/N2 per workgroup; identity
+// rings are copied when in != out).  Needs shell_fusable(n_theta, n_phi).
+// ring_c: the n_theta/2 phi cutoffs (j ascending) of each shell.  ht / hp:
+// hybrid arguments of the theta and phi passes.  The twiddle table is the one
+// of length n_phi (= 2 n_theta).
+hipError_t launch_shell_phi(bool adjoint, int n_theta, int n_phi, const double *in, double *out,
+                            const ThetaItem *shells, const double *ring_c, int n_shells,
+                            const PhiItem *rings, int n_rings, const Twiddle *tw,
+                            const double *eneg, const HybridArgs &ht, const HybridArgs &hp,
+                            hipStream_t stream);
+// n_phi = 2 n_theta and a shell fits in one workgroup's LDS (n_phi <= 128).
+bool shell_fusable(int n_theta, int n_phi);
+int shells_per_group(int n_phi);
+
 // Launch shapes (kernels.hip).  A theta workgroup has 256 lanes holding
 // theta_lines_per_group(N) complex lines, split in sub-tiles of `cols` lines,
 // one shell per sub-tile; a phi workgroup holds `lines` ring pairs.

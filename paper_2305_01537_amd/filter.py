@@ -210,6 +210,18 @@ class Plan:
                    self._lib.sphfilt_plan_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
+    def set_fused(self, enable: bool):
+        """Fuse the shells the grid allows (n_phi = 2 n_theta <= 128) or always
+        run two passes; see sphfilt_plan_set_fused."""
+        _lib.check("sphfilt_plan_set_fused", self._lib.sphfilt_plan_set_fused(self._h, int(bool(enable))))
+
+    def get_fused(self):
+        """(enabled, number of shells fused)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _lib.check("sphfilt_plan_get_fused",
+                   self._lib.sphfilt_plan_get_fused(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return bool(a.value), b.value
+
 
 class Batch:
     """Many uneven spherical patches filtered by one graph-replayed launch.

@@ -153,6 +153,39 @@ def test_workload_stats_gauss_is_never_identity():
     assert st["theta_shells_active"] == 8 and st["phi_rings_active"] == 8 * 16
 
 
+def test_workload_stats_fused_shells():
+    # n_phi = 2 n_theta <= 128: every theta-filtered shell has all its rings
+    # filtered (m_max <= l_max < n_theta = n_phi / 2), so all of them are fused
+    # and cost one round trip (16 B per point) instead of two
+    from paper_2305_01537_amd.filter import workload_stats
+    for (F, R, T, P, Lv) in ((24, 128, 64, 128, 3.0), (3, 16, 32, 64, 0.7), (2, 8, 16, 32, 1000.0)):
+        st = workload_stats(R, T, P, F, parity=1, L=Lv)
+        assert st["shells_fused"] == st["theta_shells_active"]
+        assert st["bytes_fused_inplace"] == st["bytes_forward_inplace"] - 16 * st["shells_fused"] * T * P
+    st = workload_stats(128, 64, 128, 24, parity=1, L=3.0)
+    assert st["shells_fused"] == 24 * 11           # l_max = 6 (i + 1/2) < 64 for i <= 10
+    # Gaussian shells are always filtered, hence always fused
+    st = workload_stats(8, 16, 32, 2, parity=1, L=1000.0, kind=[1, 0])
+    assert st["shells_fused"] == 8
+    # grids that do not fit (the production share) or have n_phi != 2 n_theta: none
+    for (R, T, P) in ((256, 128, 256), (8, 16, 64), (8, 32, 32)):
+        st = workload_stats(R, T, P, 2, parity=1, L=0.2)
+        assert st["shells_fused"] == 0
+        assert st["bytes_fused_inplace"] == st["bytes_forward_inplace"]
+
+
+def test_workload_stats_fused_needs_every_ring_filtered():
+    # a fisheye-like rho that grows faster than linearly keeps l_max below
+    # n_theta only on inner shells; a floor of the cutoff above n_phi/2 on the
+    # rings while l_max < n_theta is impossible for n_phi = 2 n_theta, so
+    # every active shell is fused here too; the counts follow the stats
+    from paper_2305_01537_amd.filter import workload_stats
+    rho = np.array([0.5, 1.5, 3.0, 9.0, 30.0, 100.0])
+    st = workload_stats(6, 32, 64, 1, parity=-1, L=0.9, rho=rho)
+    active = int(np.sum(np.maximum(2.0, 2 * rho * 0.9) < 32))
+    assert st["theta_shells_active"] == active == st["shells_fused"]
+
+
 def test_apply_ex_replay_needs_both_buffers(L):
     buf = ctypes.c_void_p(0x1000)
     assert L.load().sphfilt_apply_ex(None, buf, buf, 0, None, None, 1, None) == L.EINVAL

@@ -119,10 +119,12 @@ def test_identity_cutoff_is_bitwise(torch_gpu):
 def test_schedules_are_bitwise_equal_and_deterministic(torch_gpu):
     """The phi launch shape never changes the arithmetic of a line, so results are
     bitwise equal across it.  The theta tile width C decides which two meridian
-    pairs share one complex transform (k and k + C), which moves round-off only."""
+    pairs share one complex transform (k and k + C), which moves round-off only.
+    (The two-pass kernels: fused shells take neither setting.)"""
     torch = torch_gpu
     w = synth.workload("grmhd", shape=(5, 12, 64, 128))
     plan = make_plan(w.shape, w.parity, np.full(5, 0.9), w.rho)
+    plan.set_fused(False)
     xd = torch.from_numpy(w.x).cuda()
     first = plan.apply(xd).cpu().numpy()
     assert bitwise(plan.apply(xd).cpu().numpy(), first), "repeat call differs"
