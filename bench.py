@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--grmhd-only", action="store_true",
                     help="time only the grmhd grid, fused and two-pass, and print its figures "
                          "as JSON (for profiling the fused shell kernel)")
+    ap.add_argument("--short-lines-only", action="store_true",
+                    help="time only the dense short-line grids (n_phi = 32, 64, 128)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -203,6 +205,44 @@ def bench_grmhd(torch, steps, stream):
     return out
 
 
+def bench_short_lines(torch, steps, stream):
+    """Dense cutoff (every line filtered) on grids with short lines,
+    n_phi = 2 n_theta = 32, 64, 128, 24 fields and about 800 MB per buffer
+    (two rotated buffers): the throughput of each pass and of the fused
+    shells.  These are the sizes where a dense circulant on the matrix cores
+    would be cheapest; it moves the same bytes."""
+    import numpy as np
+    from paper_2305_01537_amd.filter import Plan
+    out = {}
+    F = 24
+    for N in (32, 64, 128):
+        T, P = N // 2, N
+        R = int(800e6 // (F * T * P * 8))
+        g = torch.Generator(device="cuda").manual_seed(N)
+        x0 = torch.randn((F, R, T, P), dtype=torch.float64, device="cuda", generator=g)
+        bufs = [x0, x0.clone()]
+        # rho = 1 on every shell: cutoffs at the floor, every line filtered
+        plan = Plan(R, T, P, F, parity=np.where(np.arange(F) % 3 == 2, -1, 1), L=0.2,
+                    rho=np.ones(R))
+        st = plan.stats()
+        pts = F * R * T * P
+        assert st["theta_shells_active"] == F * R and st["phi_rings_active"] == F * R * T
+        ms_t = time_loop(torch, lambda b: plan.apply_theta(b, out=b), bufs, steps, 2, stream)
+        ms_p = time_loop(torch, lambda b: plan.apply_phi(b, out=b), bufs, steps, 2, stream)
+        ms_f = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 2, stream)
+        plan.set_fused(False)
+        ms_2 = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 2, stream)
+        out[f"N{N}"] = {"shape": [F, R, T, P], "theta_GBps": 16 * pts / (ms_t * 1e-3) / 1e9,
+                        "phi_GBps": 16 * pts / (ms_p * 1e-3) / 1e9,
+                        "fused_forward_ms": ms_f, "fused_GBps": 16 * pts / (ms_f * 1e-3) / 1e9,
+                        "two_pass_forward_ms": ms_2,
+                        "fused_points_per_s": pts / (ms_f * 1e-3)}
+        plan.close()
+        del bufs, x0
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -224,6 +264,9 @@ def main():
         return 0
     if args.grmhd_only:
         print(json.dumps({"grmhd": bench_grmhd(torch, args.steps, stream)}), flush=True)
+        return 0
+    if args.short_lines_only:
+        print(json.dumps({"short_lines": bench_short_lines(torch, args.steps, stream)}), flush=True)
         return 0
 
     log("generating the share workload (24 x 256 x 128 x 256, FP64)")
@@ -308,6 +351,10 @@ def main():
         extra["calibration"] = calibrate_copy(torch, x0)
     del bufs, x0
     torch.cuda.empty_cache()
+    if not args.no_extra:
+        log("timing dense short-line grids")
+        extra["short_lines"] = bench_short_lines(torch, max(10, args.steps // 2), stream)
+        log(f"short lines: {extra['short_lines']}")
 
     cpu = None
     if not args.no_cpu_baseline:

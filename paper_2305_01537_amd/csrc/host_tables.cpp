@@ -127,7 +127,8 @@ void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parit
                 for (const PhiItem &p : rings) h->fused_c.push_back(p.c);
             } else {
                 (ident ? ti : ta).push_back(t);
-                for (const PhiItem &p : rings) ((p.flags & kFlagIdentity) ? ri : ra).push_back(p);
+                if (ident)
+                    for (const PhiItem &p : rings) ((p.flags & kFlagIdentity) ? ri : ra).push_back(p);
             }
         }
     }
@@ -170,10 +171,9 @@ void fill_stats(int n_r, int n_theta, int n_phi, int n_fields, const HostTables 
     s->bytes_forward_outofplace = 16 * (s->n_points + ph_act);
     s->bytes_adjoint_inplace = 16 * (ph_act + th_act);
     s->bytes_adjoint_outofplace = 16 * (s->n_points + th_act);
+    // every ring of a fused shell is filtered: fusing saves its phi round trip
     s->shells_fused = h.n_fused;
-    const long long fused_pts = (long long)h.n_fused * shell_pts;
-    const long long th_rest = (long long)(h.theta_active - h.n_fused) * shell_pts;
-    s->bytes_fused_inplace = 16 * (fused_pts + th_rest + 2LL * h.phi_rest_active * n_phi);
+    s->bytes_fused_inplace = s->bytes_forward_inplace - 16LL * h.n_fused * shell_pts;
 }
 
 }  // namespace sphfilt

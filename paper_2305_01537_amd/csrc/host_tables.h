@@ -12,7 +12,8 @@ namespace sphfilt {
 // Fused schedule (shell_fusable grids only): theta items [0, n_fused) are the
 // shells whose every theta line and ring is filtered, fused_c their ring-pair
 // cutoffs (n_theta/2 per shell, j ascending); phi_rest holds the phi items of
-// all other shells (active prefix of phi_rest_active items, then identity).
+// the shells the theta pass leaves alone (active prefix of phi_rest_active
+// items, then identity).
 struct HostTables {
     std::vector<ThetaItem> theta;
     std::vector<PhiItem> phi;
