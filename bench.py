@@ -66,8 +66,10 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    # the GPU takes ~10 ms of continuous work to reach its steady clock after
+    # the workload is generated on the host: 100 warm-up steps (~20 ms)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--L", type=float, default=3.0, help="cutoff scale cal-L of every field")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -311,8 +313,21 @@ def main():
         extra["adjoint_ms"] = ms_adj
         extra["adjoint_over_forward"] = ms_adj / ms_fwd
         log(f"adjoint {ms_adj:.4f} ms")
-        # per-field launches: one plan per field, two launches per field
+        # the same forward with both passes on the caller's stream (no side stream)
+        mode = plan.get_overlap()
+        plan.set_overlap(0)
+        extra["forward_one_stream_ms"] = time_loop(torch, lambda b: plan.apply(b, out=b), bufs,
+                                                   args.steps, 2, stream)
+        plan.set_overlap(mode)
+        extra["forward_again_ms"] = time_loop(torch, lambda b: plan.apply(b, out=b), bufs,
+                                              args.steps, 2, stream)
+        log(f"forward on one stream {extra['forward_one_stream_ms']:.4f} ms, "
+            f"again with overlap {extra['forward_again_ms']:.4f} ms")
+        # plain per-field launches: one plan per field, its two passes on the
+        # caller's stream
         plans = [Plan(R, T, P, 1, parity=w.parity[f:f + 1], L=w.L[f:f + 1], rho=w.rho) for f in range(F)]
+        for p_ in plans:
+            p_.set_overlap(0)
 
         def per_field(b):
             for f in range(F):

@@ -224,6 +224,27 @@ int sphfilt_plan_get_schedule(sphfilt_plan plan, int *theta_cols, int *phi_lines
 int sphfilt_plan_set_fused(sphfilt_plan plan, int enable);
 int sphfilt_plan_get_fused(sphfilt_plan plan, int *enable, int *shells_fused);
 
+/*
+ * Overlapped passes (in place, shells not fused).  The rings of shells whose
+ * theta mask is all ones do not depend on the theta pass.  An overlapped
+ * in-place call runs them on a second stream owned by the plan, alongside the
+ * theta pass and the rings of the theta-filtered shells on the caller's
+ * stream; the caller's stream then waits for that stream (event fork and
+ * join, so the call stays stream-ordered and can be captured in a HIP graph).
+ * Each ring's arithmetic is unchanged: results are bitwise those of the
+ * two-pass path.  The stream and two events are created on the first such
+ * call (on the plan's device) and released by sphfilt_plan_destroy;
+ * enqueueing takes a lock of the plan.
+ *   mode  0: both passes on the caller's stream;
+ *         1 (the default): overlap when those rings move at least 128 MiB
+ *           (below that the fork and join cost more than they hide);
+ *         2: overlap whenever there is theta work and such a ring.
+ * set_overlap returns SPHFILT_EINVAL for other values; get_overlap needs a
+ * non-NULL output.
+ */
+int sphfilt_plan_set_overlap(sphfilt_plan plan, int mode);
+int sphfilt_plan_get_overlap(sphfilt_plan plan, int *mode);
+
 /* ======================================================================
  * Batched filter: many uneven spherical patches in one launch.
  *

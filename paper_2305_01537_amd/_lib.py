@@ -56,6 +56,8 @@ SIGNATURES = {
     "sphfilt_plan_get_schedule": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
     "sphfilt_plan_set_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sphfilt_plan_get_fused": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
+    "sphfilt_plan_set_overlap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sphfilt_plan_get_overlap": (ctypes.c_int, [ctypes.c_void_p, c_int_p]),
     "sphfilt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                             ctypes.POINTER(PatchDesc), ctypes.c_char_p]),
     "sphfilt_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),

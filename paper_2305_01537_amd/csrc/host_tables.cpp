@@ -129,6 +129,9 @@ void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parit
                 (ident ? ti : ta).push_back(t);
                 if (ident)
                     for (const PhiItem &p : rings) ((p.flags & kFlagIdentity) ? ri : ra).push_back(p);
+                else
+                    for (const PhiItem &p : rings)
+                        if (!(p.flags & kFlagIdentity)) h->phi_in.push_back(p);
             }
         }
     }

@@ -13,7 +13,8 @@ namespace sphfilt {
 // shells whose every theta line and ring is filtered, fused_c their ring-pair
 // cutoffs (n_theta/2 per shell, j ascending); phi_rest holds the phi items of
 // the shells the theta pass leaves alone (active prefix of phi_rest_active
-// items, then identity).
+// items, then identity), on every grid; phi_in the active phi items of the
+// theta-filtered shells that are not fused.
 struct HostTables {
     std::vector<ThetaItem> theta;
     std::vector<PhiItem> phi;
@@ -23,6 +24,7 @@ struct HostTables {
     std::vector<double> fused_c;
     std::vector<PhiItem> phi_rest;
     int phi_rest_active = 0;
+    std::vector<PhiItem> phi_in;
 };
 
 bool fault(const char *what);

@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,6 +39,18 @@ struct DeviceTables {
     double *eneg = nullptr;
     double *fused_c = nullptr;
     PhiItem *phi_rest = nullptr;
+    PhiItem *phi_in = nullptr;
+};
+
+// A second stream of the plan, for ring pairs that do not depend on the theta
+// pass; fork and join events tie it to the caller's stream.  Created on first
+// use; the mutex covers the fork-launch-join sequence, so that each call's
+// waits refer to its own event records.
+struct SideStream {
+    std::mutex m;
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    int state = 0;          // 0: not created, 1: ready, -1: creation failed
 };
 
 }  // namespace
@@ -49,7 +62,9 @@ struct sphfilt_plan_s {
     DeviceTables dev;
     int theta_cols, phi_lines;
     int fused;              // fuse shells where the grid allows it
+    int overlap;            // 0 off, 1 auto, 2 always: independent rings on the side stream
     HybridArgs hybrid;      // detector parameters; dec / replay set per call
+    SideStream side;
 };
 
 namespace {
@@ -63,6 +78,7 @@ void free_device(DeviceTables *d)
     if (d->eneg) (void)hipFree(d->eneg);
     if (d->fused_c) (void)hipFree(d->fused_c);
     if (d->phi_rest) (void)hipFree(d->phi_rest);
+    if (d->phi_in) (void)hipFree(d->phi_in);
     *d = DeviceTables{};
 }
 
@@ -127,6 +143,82 @@ int apply_fused(sphfilt_plan p, bool adjoint, const double *in, double *out, con
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
 
+bool side_ready(SideStream &ss)
+{
+    if (ss.state == 0) {
+        ss.state = -1;
+        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) {
+            ss.stream = nullptr;
+            return false;
+        }
+        if (hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess)
+            return false;
+        ss.state = 1;
+    }
+    return ss.state == 1;
+}
+
+void side_destroy(SideStream &ss)
+{
+    if (ss.join) (void)hipEventDestroy(ss.join);
+    if (ss.fork) (void)hipEventDestroy(ss.fork);
+    if (ss.stream) (void)hipStreamDestroy(ss.stream);
+    ss.stream = nullptr;
+    ss.fork = ss.join = nullptr;
+    ss.state = 0;
+}
+
+// Overlap needs theta work and independent ring pairs; in the automatic mode
+// the independent rings must also move enough bytes to hide the fork and
+// join (a few microseconds each on the device timeline).
+constexpr long long kOverlapMinBytes = 128LL << 20;
+
+bool overlap_pays(sphfilt_plan p)
+{
+    const HostTables &t = p->host;
+    if (p->overlap == 0 || t.n_fused != 0 || t.theta_active == 0 || t.phi_rest_active == 0)
+        return false;
+    const long long rest_bytes = 16LL * 2 * t.phi_rest_active * p->n_phi;
+    return p->overlap == 2 || rest_bytes >= kOverlapMinBytes;
+}
+
+// In place: the ring pairs of shells the theta pass leaves alone do not
+// depend on it, so they run on the side stream while the caller's stream runs
+// the theta pass and the rings of the theta-filtered shells (in the call's
+// order); the caller's stream then waits for the side stream.  Returns
+// SPHFILT_EUNSUPPORTED when the side stream cannot be created (the caller
+// then runs two passes).
+int apply_overlap(sphfilt_plan p, bool adjoint, double *x, const Decisions &d, hipStream_t s)
+{
+    const HostTables &t = p->host;
+    std::lock_guard<std::mutex> lock(p->side.m);
+    if (!side_ready(p->side)) return SPHFILT_EUNSUPPORTED;
+    HybridArgs ht = p->hybrid, hp = p->hybrid;
+    ht.replay = hp.replay = d.replay;
+    ht.dec = d.theta;
+    hp.dec = d.phi;
+    hipStream_t side = p->side.stream;
+    hipError_t e = hipEventRecord(p->side.fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, p->side.fork, 0);
+    auto theta = [&]() {
+        return launch_theta(2 * p->n_theta, p->theta_cols, x, x, p->dev.theta, t.theta_active,
+                            p->n_theta, p->n_phi, p->dev.tw_theta, p->dev.eneg, ht, s);
+    };
+    auto rings_in = [&]() {
+        return launch_phi(p->n_phi, p->phi_lines, x, x, p->dev.phi_in, (int)t.phi_in.size(),
+                          p->n_theta, p->dev.tw_phi, p->dev.eneg, hp, s);
+    };
+    if (e == hipSuccess) e = adjoint ? rings_in() : theta();
+    if (e == hipSuccess)
+        e = launch_phi(p->n_phi, p->phi_lines, x, x, p->dev.phi_rest, t.phi_rest_active,
+                       p->n_theta, p->dev.tw_phi, p->dev.eneg, hp, side);
+    if (e == hipSuccess) e = adjoint ? theta() : rings_in();
+    if (e == hipSuccess) e = hipEventRecord(p->side.join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->side.join, 0);
+    return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
+}
+
 // Two passes in the given order.  Out of place, the first pass runs over all
 // items (copying identity lines) and the second works in place on `out`.
 int apply_two(sphfilt_plan p, Pass first, Pass second, const double *in, double *out,
@@ -139,6 +231,10 @@ int apply_two(sphfilt_plan p, Pass first, Pass second, const double *in, double 
     hipStream_t s = (hipStream_t)stream;
     if (p->fused && p->host.n_fused > 0) {
         rc = apply_fused(p, first == Pass::Phi, in, out, d, s);
+        if (rc != SPHFILT_EUNSUPPORTED) return rc;
+    }
+    if (overlap_pays(p) && in == out) {
+        rc = apply_overlap(p, first == Pass::Phi, out, d, s);
         if (rc != SPHFILT_EUNSUPPORTED) return rc;
     }
     const bool inplace = in == out;
@@ -194,6 +290,7 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
     p->hybrid = hybrid_args(cut, n_fields);
     p->phi_lines = default_phi_lines(n_phi);
     p->fused = 1;
+    p->overlap = 1;
     try {
         build_items(n_r, n_theta, n_phi, n_fields, parity, cut, &p->host);
         if (hipGetDevice(&p->device) != hipSuccess) rc = SPHFILT_EDEVICE;
@@ -204,6 +301,7 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
         if (!rc) rc = upload(&p->dev.eneg, exp_table());
         if (!rc) rc = upload(&p->dev.fused_c, p->host.fused_c);
         if (!rc) rc = upload(&p->dev.phi_rest, p->host.phi_rest);
+        if (!rc) rc = upload(&p->dev.phi_in, p->host.phi_in);
     } catch (const std::bad_alloc &) {
         rc = SPHFILT_ENOMEM;
     }
@@ -221,6 +319,7 @@ int sphfilt_plan_destroy(sphfilt_plan plan)
     if (!plan) return SPHFILT_OK;
     {
         DeviceGuard g(plan->device);
+        side_destroy(plan->side);
         free_device(&plan->dev);
     }
     delete plan;
@@ -287,6 +386,20 @@ int sphfilt_plan_set_fused(sphfilt_plan plan, int enable)
 {
     if (!plan || (enable != 0 && enable != 1)) return SPHFILT_EINVAL;
     plan->fused = enable;
+    return SPHFILT_OK;
+}
+
+int sphfilt_plan_set_overlap(sphfilt_plan plan, int mode)
+{
+    if (!plan || mode < 0 || mode > 2) return SPHFILT_EINVAL;
+    plan->overlap = mode;
+    return SPHFILT_OK;
+}
+
+int sphfilt_plan_get_overlap(sphfilt_plan plan, int *mode)
+{
+    if (!plan || !mode) return SPHFILT_EINVAL;
+    *mode = plan->overlap;
     return SPHFILT_OK;
 }
 

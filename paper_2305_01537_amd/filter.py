@@ -215,6 +215,17 @@ class Plan:
         run two passes; see sphfilt_plan_set_fused."""
         _lib.check("sphfilt_plan_set_fused", self._lib.sphfilt_plan_set_fused(self._h, int(bool(enable))))
 
+    def set_overlap(self, mode: int):
+        """In place, run the rings that do not depend on the theta pass on a
+        second stream of the plan: 0 never, 1 when they move >= 128 MiB (the
+        default), 2 always; see sphfilt_plan_set_overlap."""
+        _lib.check("sphfilt_plan_set_overlap", self._lib.sphfilt_plan_set_overlap(self._h, int(mode)))
+
+    def get_overlap(self) -> int:
+        a = ctypes.c_int()
+        _lib.check("sphfilt_plan_get_overlap", self._lib.sphfilt_plan_get_overlap(self._h, ctypes.byref(a)))
+        return a.value
+
     def get_fused(self):
         """(enabled, number of shells fused)."""
         a, b = ctypes.c_int(), ctypes.c_int()
