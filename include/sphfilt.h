@@ -124,9 +124,10 @@ typedef struct {
  *   cut     cutoff parameters, see sphfilt_cutoff.
  * Builds the cutoff tables, the lists of non-identity lines and the twiddle
  * tables on the host, then allocates and uploads them to the current HIP
- * device.  The plan owns that device memory until sphfilt_plan_destroy and
- * keeps no scratch, so one plan may be applied concurrently on several
- * streams.
+ * device (and, where overlap can apply, creates the plan's second stream; see
+ * sphfilt_plan_set_overlap).  The plan owns that device memory until
+ * sphfilt_plan_destroy and keeps no scratch, so one plan may be applied
+ * concurrently on several streams.
  * Returns SPHFILT_EINVAL for n_* <= 0, odd n_phi, NULL pointers, parity not
  * +-1, non-finite or non-positive rho / L, unknown kind, bad floor;
  * SPHFILT_EUNSUPPORTED for sizes outside this build; SPHFILT_ENOMEM /
@@ -232,9 +233,11 @@ int sphfilt_plan_get_fused(sphfilt_plan plan, int *enable, int *shells_fused);
  * stream; the caller's stream then waits for that stream (event fork and
  * join, so the call stays stream-ordered and can be captured in a HIP graph).
  * Each ring's arithmetic is unchanged: results are bitwise those of the
- * two-pass path.  The stream and two events are created on the first such
- * call (on the plan's device) and released by sphfilt_plan_destroy;
- * enqueueing takes a lock of the plan.
+ * two-pass path.  The stream and two events are created with the plan (on
+ * its device) when the plan has theta-filtered shells that are not fused and
+ * rings independent of them, and released by sphfilt_plan_destroy; no call
+ * creates them, so a call can be captured in a HIP graph.  Enqueueing takes a
+ * lock of the plan.
  *   mode  0: both passes on the caller's stream;
  *         1 (the default): overlap when those rings move at least 128 MiB
  *           (below that the fork and join cost more than they hide);

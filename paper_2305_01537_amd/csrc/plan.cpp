@@ -43,9 +43,11 @@ struct DeviceTables {
 };
 
 // A second stream of the plan, for ring pairs that do not depend on the theta
-// pass; fork and join events tie it to the caller's stream.  Created on first
-// use; the mutex covers the fork-launch-join sequence, so that each call's
-// waits refer to its own event records.
+// pass; fork and join events tie it to the caller's stream.  Created with the
+// plan when its lists allow overlap (so that no stream is created inside a
+// caller's graph capture), else on first use; the mutex covers the
+// fork-launch-join sequence, so that each call's waits refer to its own event
+// records.
 struct SideStream {
     std::mutex m;
     hipStream_t stream = nullptr;
@@ -305,7 +307,12 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
     } catch (const std::bad_alloc &) {
         rc = SPHFILT_ENOMEM;
     }
+    const HostTables &t = p->host;
+    if (!rc && t.n_fused == 0 && t.theta_active > 0 && t.phi_rest_active > 0 &&
+        !side_ready(p->side))
+        rc = SPHFILT_EDEVICE;
     if (rc) {
+        side_destroy(p->side);
         free_device(&p->dev);
         delete p;
         return rc;

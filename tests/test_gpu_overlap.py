@@ -117,7 +117,7 @@ def test_overlap_in_a_captured_graph(torch_gpu):
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        plan.apply(buf, out=buf)                 # creates the side stream outside the capture
+        plan.apply(buf, out=buf)                 # warm-up call before the capture
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
