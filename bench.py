@@ -5,9 +5,10 @@ One step = one forward double FFT filter (theta-pass then phi-pass) over the
 production share: 24 FP64 fields on a 256 x 128 x 256 (r, theta, phi) grid,
 with the paper's cutoff (cal-L = 3 on a uniform cell-centred radial grid),
 applied in place -- the way an evolution code filters its state once per
-Runge-Kutta substep.  Inputs are seeded synthetic fields already resident in
-HBM; four copies are rotated so no step finds its data in the 256 MB
-Infinity Cache from the step before.
+Runge-Kutta substep, with the plan's default schedule (rings that do not
+depend on the theta pass overlapped on a second stream).  Inputs are seeded
+synthetic fields already resident in HBM; four copies are rotated so no step
+finds its data in the 256 MB Infinity Cache from the step before.
 
 Prints ONE JSON line:
   value         filtered field-points per second (whole job, one GPU)
@@ -15,9 +16,10 @@ Prints ONE JSON line:
                 its average launch time (HIP events on the launch stream),
                 against the 8 TB/s HBM3E peak
   cpu_baseline  the CPU oracle (direct DFTs) on a bounded sample of the same
-                workload, on this host's cores
-  extra         adjoint/forward ratio, per-field launches, the dense-cutoff
-                variant, the grmhd-sized workload
+                workload, on this host's cores (and on one thread)
+  extra         adjoint/forward ratio, the forward on one stream, per-field
+                launches, the dense-cutoff variant, the grmhd grid (fused
+                shells), the 64-patch batch, dense short-line grids
 """
 import argparse
 import json
@@ -122,10 +124,32 @@ def cpu_baseline(w, L, budget_s):
     t = time.perf_counter()
     oracle.forward(sub, parity=w.parity[:n_f], rho=w.rho[:n_r], L=L)
     dt = time.perf_counter() - t
+    # one thread, on the first shells of field 0 (about budget/4 seconds)
+    prev = oracle.set_threads(1)
+    n1 = int(max(1, min(R, budget_s / 4 / max(one * threads, 1e-6))))
+    sub1 = np.ascontiguousarray(w.x[:1, :n1])
+    t = time.perf_counter()
+    oracle.forward(sub1, parity=w.parity[:1], rho=w.rho[:n1], L=L)
+    dt1 = time.perf_counter() - t
+    oracle.set_threads(prev)
     return {"value": sub.size / dt, "unit": "field-points/s", "cores": threads, "kind": "oracle",
             "sample": f"fields 0..{n_f - 1} x shells 0..{n_r - 1} of the share workload "
                       f"({sub.size} points, cal-L={L}), forward filter (theta then phi, "
-                      f"direct DFTs), {dt:.1f} s"}
+                      f"direct DFTs), {dt:.1f} s",
+            "host_cpu": host_cpu(),
+            "single_thread": {"value": sub1.size / dt1, "unit": "field-points/s",
+                              "sample": f"field 0 x shells 0..{n1 - 1} ({sub1.size} points), "
+                                        f"{dt1:.1f} s"}}
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            names = [l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")]
+        return f"{names[0]} ({len(names)} logical CPUs visible)" if names else None
+    except OSError:
+        return None
 
 
 def calibrate_copy(torch, x, reps=3):

@@ -43,6 +43,8 @@ def _load():
         lib.orc_sin_theta.restype = ctypes.c_double
         lib.orc_set_detector.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.orc_set_detector.restype = None
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = ctypes.c_int
         lib.orc_shock_detected.argtypes = [dp, ctypes.c_int]
         lib.orc_shock_detected.restype = ctypes.c_int
         ucp = ctypes.POINTER(ctypes.c_ubyte)
@@ -124,6 +126,12 @@ def adjoint(x, parity=1, rho=None, L=3.0, kind=EXP, floor_modes=2.0, return_imag
 def set_detector(eps: float = 1e-12, threshold: float = 0.95) -> None:
     """Parameters of Jameson's detector used by the hybrid filter."""
     _load().orc_set_detector(float(eps), float(threshold))
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's loops over lines (0: all processors); returns the
+    previous setting.  For timing only."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def shock_detected(line) -> bool:

@@ -47,6 +47,7 @@
  *   forward DFT unnormalised, inverse scaled by 1/N.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -70,6 +71,16 @@ void orc_set_detector(double eps, double threshold)
 {
     orc_det_eps = eps;
     orc_det_threshold = threshold;
+}
+
+/* Threads of the parallel loops over lines (n <= 0: all processors); returns
+ * the previous setting.  Only for timing the oracle: results do not depend on
+ * it (each line is computed by one thread in a fixed order). */
+int orc_set_threads(int n)
+{
+    const int prev = omp_get_max_threads();
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+    return prev;
 }
 
 /* Jameson's detector on one periodic line: 1 if any cell has sigma >= threshold. */

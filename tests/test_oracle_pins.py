@@ -562,3 +562,16 @@ def test_hybrid_detector_is_periodic_and_has_a_threshold(oracle_mod):
         assert not oracle_mod.shock_detected(step)
     finally:
         oracle_mod.set_detector()
+
+
+def test_oracle_results_do_not_depend_on_threads(oracle_mod):
+    # the thread count only times the oracle (the benchmark's single-thread
+    # baseline): each line is computed by one thread in a fixed order
+    x = np.random.default_rng(12).standard_normal((2, 5, 16, 32))
+    a = oracle_mod.forward(x, parity=[1, -1], L=[0.7, 1.3])
+    prev = oracle_mod.set_threads(1)
+    try:
+        b = oracle_mod.forward(x, parity=[1, -1], L=[0.7, 1.3])
+    finally:
+        oracle_mod.set_threads(prev)
+    assert np.array_equal(a, b)
