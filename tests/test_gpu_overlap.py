@@ -145,3 +145,31 @@ def test_set_overlap_modes(torch_gpu):
         plan.set_overlap(m)
         assert plan.get_overlap() == m
     plan.close()
+
+
+def test_overlap_records_and_replays_hybrid_decisions(torch_gpu):
+    """With the other fields' idle-shell rings on the second stream, the hybrid
+    field's decisions (a hybrid shell is never idle) and the replayed adjoint
+    are bitwise those of the one-stream call."""
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Plan
+    shape, kind, L = CASES[1]
+    F, R, T, P = shape
+    x, parity = fields(shape, 151)
+    x[2, 6, 3, :] = np.where(np.arange(P) < 40, 0.0, 1.5)      # a ring jump in the hybrid field
+    plan = Plan(R, T, P, F, parity=parity, L=np.array(L), kind=np.array(kind, dtype=np.int32))
+    g = np.random.default_rng(152).standard_normal(shape)
+    res = {}
+    for ov in (2, 0):
+        plan.set_overlap(ov)
+        th, ph = plan.decision_buffers()
+        y = torch.from_numpy(x).cuda()
+        plan.apply_ex(y, out=y, theta_dec=th, phi_dec=ph)
+        z = torch.from_numpy(g).cuda()
+        plan.apply_ex(z, out=z, adjoint=True, theta_dec=th, phi_dec=ph, replay=True)
+        torch.cuda.synchronize()
+        res[ov] = [t.cpu().numpy() for t in (y, th, ph, z)]
+    for a, b in zip(res[2], res[0]):
+        assert np.array_equal(a, b)
+    assert res[2][2][2].any()
+    plan.close()

@@ -172,7 +172,9 @@ def test_grmhd_full_forward_adjoint(torch_gpu):
 
 def test_share_full_size_sampled_shells(torch_gpu):
     """The 24 x 256 x 128 x 256 production share, in the launch shape the benchmark
-    times (in place, default schedule); the oracle checks sampled whole shells."""
+    times (in place, default schedule: at cal-L = 3 the rings of shells the theta
+    pass leaves alone run on the plan's second stream); the oracle checks
+    sampled whole shells, filtered (5, 20) and untouched (11, 21) by theta."""
     torch = torch_gpu
     w = synth.workload("share")
     print(f"[gpu] share {w.shape}", flush=True)
@@ -180,7 +182,8 @@ def test_share_full_size_sampled_shells(torch_gpu):
         plan = make_plan(w.shape, w.parity, np.full(24, L), w.rho)
         xd = torch.from_numpy(w.x).cuda()
         plan.apply(xd, out=xd)
-        ya = plan.apply_adjoint(torch.from_numpy(w.x).cuda())
+        ya = torch.from_numpy(w.x).cuda()
+        plan.apply_adjoint(ya, out=ya)
         torch.cuda.synchronize()
         fwd, adj = xd.cpu().numpy(), ya.cpu().numpy()
         del xd, ya
