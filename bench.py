@@ -179,6 +179,12 @@ def bench_patches(torch, steps, stream):
     st = batch.stats()
     ms_b = time_loop(torch, lambda b: batch.apply(b, outs=b), [xs], steps, 3, stream)
     ms_ba = time_loop(torch, lambda b: batch.apply(b, outs=b, adjoint=True), [xs], steps, 3, stream)
+    # the tuner's choice of fused items, and the same schedule with the other choice
+    tuned_fused = batch.get_fused()[0]
+    batch.set_fused(not tuned_fused)
+    st_alt = batch.stats()
+    ms_alt = time_loop(torch, lambda b: batch.apply(b, outs=b), [xs], steps, 3, stream)
+    batch.set_fused(tuned_fused)
     plans = [Plan(p.n_r, p.n_theta, p.n_phi, p.n_fields, parity=p.parity, L=p.L, rho=p.rho)
              for p in pts]
 
@@ -189,10 +195,14 @@ def bench_patches(torch, steps, stream):
     assert batch.status() == 0
     out = {
         "patches": len(pts), "points": st["n_points"],
-        "algorithmic_bytes": st["bytes_forward_inplace"],
+        "algorithmic_bytes": st["bytes_fused_inplace"],
         "batched_forward_ms": ms_b, "batched_adjoint_ms": ms_ba, "per_patch_launch_ms": ms_pp,
+        "tuned_fused_items": tuned_fused, "shells_fused": st["shells_fused"],
+        "other_setting": {"fused_items": not tuned_fused, "forward_ms": ms_alt,
+                          "shells_fused": st_alt["shells_fused"],
+                          "algorithmic_bytes": st_alt["bytes_fused_inplace"]},
         "batched_points_per_s": st["n_points"] / (ms_b * 1e-3),
-        "batched_GBps": st["bytes_forward_inplace"] / (ms_b * 1e-3) / 1e9,
+        "batched_GBps": st["bytes_fused_inplace"] / (ms_b * 1e-3) / 1e9,
         "batched_over_per_patch_speedup": ms_pp / ms_b,
         "schedule": sched,
     }

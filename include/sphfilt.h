@@ -327,8 +327,25 @@ int sphfilt_batch_get_schedule(sphfilt_batch batch, int *split, int *workgroups_
  * second-pass item gave up waiting (a library bug; results are invalid). */
 int sphfilt_batch_status(sphfilt_batch batch, int *device_error);
 
-/* Work and traffic figures summed over the batch's patches (host only). */
+/* Work and traffic figures summed over the batch's patches (host only);
+ * shells_fused and bytes_fused_inplace follow sphfilt_batch_set_fused. */
 int sphfilt_batch_stats(sphfilt_batch batch, sphfilt_stats *out);
+
+/*
+ * Fused shells in a batch (as sphfilt_plan_set_fused): a patch with
+ * n_phi = 2 * n_theta <= 128 runs its theta-filtered shells as fused items
+ * (one HBM round trip for both passes) and the rings of its other shells in
+ * the first pass, so it has no second-pass work.
+ *   enable  1 or 0 (every patch in two passes).  The autotuner times both
+ *           (when some patch allows fused items) with every schedule and keeps
+ *           the fastest; untuned batches start with 1.
+ * Changing it drops the batch's captured graphs and work lists (they are
+ * rebuilt on the next call) after synchronising the device.  get_fused
+ * reports the setting and the number of shells fused (NULL outputs are
+ * skipped).
+ */
+int sphfilt_batch_set_fused(sphfilt_batch batch, int enable);
+int sphfilt_batch_get_fused(sphfilt_batch batch, int *enable, int *shells_fused);
 
 /* Human-readable text of a status code (static storage). */
 const char *sphfilt_status_string(int status);

@@ -68,6 +68,8 @@ SIGNATURES = {
     "sphfilt_batch_get_schedule": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_double_p]),
     "sphfilt_batch_status": (ctypes.c_int, [ctypes.c_void_p, c_int_p]),
     "sphfilt_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "sphfilt_batch_set_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sphfilt_batch_get_fused": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
     "sphfilt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sphfilt_version": (ctypes.c_char_p, []),
 }

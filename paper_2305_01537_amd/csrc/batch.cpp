@@ -36,6 +36,8 @@ struct PatchHost {
     int n_r, n_theta, n_phi, n_fields;
     HostTables tables;
     int theta_off = 0, phi_off = 0;   // into the concatenated item arrays
+    int phi_rest_off = 0;             // the phi items of theta-idle shells
+    int fc_off = 0;                   // fused shells' ring cutoffs
     int shell_base = 0;               // first global shell id
     int cols = 0;                     // theta sub-tile width (meridian pairs)
     long long n_points = 0;
@@ -71,6 +73,8 @@ struct sphfilt_batch_s {
     std::vector<PatchHost> patches;
     ThetaItem *d_th = nullptr;
     PhiItem *d_ph = nullptr;
+    double *d_fc = nullptr;
+    int fused = 1;                     // fused items for patches that allow them
     BatchPatchDev *d_patches = nullptr;
     double *d_eneg = nullptr;
     std::map<int, Twiddle *> d_tw;
@@ -127,11 +131,12 @@ std::string hex64(uint64_t v)
     return buf;
 }
 
+
 // ---- the JSON tuning cache: one entry per line -------------------------
 //   {"sphfilt_tune_cache": 1, "entries": [
-//    {"sig": "<16 hex>", "arch": "gfx950", "split": 0, "wpc": 2, "us": 812.5},
+//    {"sig": "<16 hex>", "arch": "gfx950", "split": 0, "wpc": 2, "fused": 1, "us": 812.5},
 //   ...]}
-bool cache_lookup(const char *path, const std::string &sig, int *split, int *wpc)
+bool cache_lookup(const char *path, const std::string &sig, int *split, int *wpc, int *fused)
 {
     std::ifstream f(path);
     if (!f) return false;
@@ -143,13 +148,15 @@ bool cache_lookup(const char *path, const std::string &sig, int *split, int *wpc
         if (a == std::string::npos || b == std::string::npos) return false;
         *split = std::atoi(line.c_str() + a + 9);
         *wpc = std::atoi(line.c_str() + b + 7);
-        return (*split == 0 || *split == 1) && *wpc >= -1 && *wpc <= 64;
+        const size_t c = line.find("\"fused\": ");
+        *fused = c == std::string::npos ? 1 : std::atoi(line.c_str() + c + 9);
+        return (*split == 0 || *split == 1) && *wpc >= -1 && *wpc <= 64 && (*fused == 0 || *fused == 1);
     }
     return false;
 }
 
 bool cache_store(const char *path, const std::string &sig, const std::string &arch, int split,
-                 int wpc, double us)
+                 int wpc, int fused, double us)
 {
     std::vector<std::string> keep;
     {
@@ -166,7 +173,7 @@ bool cache_store(const char *path, const std::string &sig, const std::string &ar
     }
     std::ostringstream e;
     e << "  {\"sig\": \"" << sig << "\", \"arch\": \"" << arch << "\", \"split\": " << split
-      << ", \"wpc\": " << wpc << ", \"us\": " << us << "}";
+      << ", \"wpc\": " << wpc << ", \"fused\": " << fused << ", \"us\": " << us << "}";
     keep.push_back(e.str());
     const std::string tmp = std::string(path) + ".tmp";
     {
@@ -201,7 +208,7 @@ void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
                 shells->push_back(p.shell_base + p.tables.theta[(size_t)(g * S + u)].shell);
             for (int tile = 0; tile < T; ++tile)
                 work->push_back(BatchWork{pi, 0, (int16_t)second, p.theta_off + g * S, (int16_t)nv,
-                                          (int16_t)tile, off, nv});
+                                          (int16_t)tile, off, nv, 0, 0});
         }
     } else {
         const int n = all ? (int)p.tables.phi.size() : p.tables.phi_active;
@@ -216,9 +223,40 @@ void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
             const int off = (int)shells->size();
             shells->insert(shells->end(), s.begin(), s.end());
             work->push_back(BatchWork{pi, 1, (int16_t)second, p.phi_off + c * L, (int16_t)nv, 0, off,
-                                      (int)s.size()});
+                                      (int)s.size(), 0, 0});
         }
     }
+}
+
+// A patch whose theta-filtered shells are all fused (n_phi = 2 n_theta <= 128,
+// see build_items) runs entirely in the first pass: groups of whole shells
+// (both passes, add_fused_shells), and the ring pairs of its theta-idle shells
+// (add_rest_rings; out of place also their identity rings, copied).  Nothing
+// waits for these items.
+bool patch_fused(const sphfilt_batch b, const PatchHost &p)
+{
+    return b->fused && p.tables.n_fused > 0 && p.tables.n_fused == p.tables.theta_active;
+}
+
+void add_fused_shells(const sphfilt_batch b, int pi, bool adjoint, std::vector<BatchWork> *work)
+{
+    const PatchHost &p = b->patches[(size_t)pi];
+    const int S = shells_per_group(p.n_phi), lines = p.n_theta / 2;
+    for (int g = 0; g * S < p.tables.n_fused; ++g) {
+        const int nv = std::min(S, p.tables.n_fused - g * S);
+        work->push_back(BatchWork{pi, 2, 0, p.theta_off + g * S, (int16_t)nv, (int16_t)adjoint, 0, 0,
+                                  p.fc_off + g * S * lines, 0});
+    }
+}
+
+void add_rest_rings(const sphfilt_batch b, int pi, bool all, std::vector<BatchWork> *work)
+{
+    const PatchHost &p = b->patches[(size_t)pi];
+    const int n = all ? (int)p.tables.phi_rest.size() : p.tables.phi_rest_active;
+    const int L = default_phi_lines(p.n_phi);
+    for (int c = 0; c * L < n; ++c)
+        work->push_back(BatchWork{pi, 1, 0, p.phi_rest_off + c * L, (int16_t)std::min(L, n - c * L), 0,
+                                  0, 0, 0, 0});
 }
 
 int build_mode(sphfilt_batch b, int mode)
@@ -228,11 +266,20 @@ int build_mode(sphfilt_batch b, int mode)
     const bool adjoint = mode & 1, inplace = mode & 2;
     std::vector<BatchWork> work;
     std::vector<int> shells;
+    // fused shell groups first: they hold a workgroup longest (a whole shell,
+    // both passes), so they start before the short items rather than trail them
     for (int p = 0; p < (int)b->patches.size(); ++p)
-        add_pass(b, p, !adjoint, !inplace, false, &work, &shells);
+        if (patch_fused(b, b->patches[(size_t)p])) add_fused_shells(b, p, adjoint, &work);
+    for (int p = 0; p < (int)b->patches.size(); ++p) {
+        if (patch_fused(b, b->patches[(size_t)p]))
+            add_rest_rings(b, p, !inplace, &work);
+        else
+            add_pass(b, p, !adjoint, !inplace, false, &work, &shells);
+    }
     const int n_first = (int)work.size();
     for (int p = 0; p < (int)b->patches.size(); ++p)
-        add_pass(b, p, adjoint, false, true, &work, &shells);
+        if (!patch_fused(b, b->patches[(size_t)p]))
+            add_pass(b, p, adjoint, false, true, &work, &shells);
     std::vector<int> need((size_t)std::max(1, b->n_shells_total), 0);
     for (int k = 0; k < n_first; ++k)
         for (int i = 0; i < work[(size_t)k].n_shells; ++i) ++need[(size_t)shells[(size_t)(work[(size_t)k].shell_off + i)]];
@@ -271,15 +318,15 @@ int record(sphfilt_batch b, const ModeWork &m, const GraphEntry &g, hipStream_t 
     if (e != hipSuccess) return SPHFILT_EDEVICE;
     if (g.split) {
         e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
-                         m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg,
+                         b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg,
                          0, kSpinLimit, b->hybrid, s);
         if (e == hipSuccess)
             e = launch_batch(grid, m.d_work + m.n_first, m.n_work - m.n_first, b->d_patches, g.d_ins,
-                             g.d_outs, b->d_th, b->d_ph, m.d_shells, b->d_counters, m.d_need,
+                             g.d_outs, b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
                              b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid, s);
     } else {
         e = launch_batch(grid, m.d_work, m.n_work, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
-                         m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg, 1,
+                         b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg, 1,
                          kSpinLimit, b->hybrid, s);
     }
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
@@ -335,7 +382,8 @@ int get_graph(sphfilt_batch b, int mode, const double *const *ins, double *const
     return SPHFILT_OK;
 }
 
-void free_batch(sphfilt_batch b)
+// Drop the captured graphs and the work lists (rebuilt on the next call).
+void free_work(sphfilt_batch b)
 {
     for (GraphEntry &g : b->graphs) free_graph(&g);
     b->graphs.clear();
@@ -345,9 +393,15 @@ void free_batch(sphfilt_batch b)
         if (m.d_need) (void)hipFree(m.d_need);
         m = ModeWork{};
     }
+}
+
+void free_batch(sphfilt_batch b)
+{
+    free_work(b);
     for (auto &kv : b->d_tw) (void)hipFree(kv.second);
     b->d_tw.clear();
-    void *ptrs[] = {b->d_th, b->d_ph, b->d_patches, b->d_eneg, b->d_counters, b->d_tickets, b->d_error};
+    void *ptrs[] = {b->d_th, b->d_ph, b->d_fc, b->d_patches, b->d_eneg, b->d_counters, b->d_tickets,
+                    b->d_error};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
@@ -442,19 +496,30 @@ int tune(sphfilt_batch b, const char *cache_path)
     if (hipMemset(scratch, 0, sizeof(double) * (size_t)total) != hipSuccess ||
         hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
         rc = SPHFILT_EDEVICE;
-    int best_split = 0, best_wpc = -1;
+    int best_split = 0, best_wpc = -1, best_fused = b->fused;
     double best = 1e300;
-    for (int split = 0; split <= 1 && !rc; ++split) {
-        for (int wpc = -1; wpc <= b->max_wpc && !rc; ++wpc) {
-            if (wpc == 0) continue;
-            b->split = split;
-            b->wpc = wpc;
-            double us = 0;
-            rc = time_schedule(b, bufs, s, 5, &us);
-            if (!rc && us < best) {
-                best = us;
-                best_split = split;
-                best_wpc = wpc;
+    // fused items only matter when some patch has them
+    bool any_fused = false;
+    for (const PatchHost &p : b->patches) any_fused |= p.tables.n_fused > 0 && p.tables.n_fused == p.tables.theta_active;
+    for (int fz = any_fused ? 1 : b->fused; fz >= (any_fused ? 0 : b->fused) && !rc; --fz) {
+        if (fz != b->fused) {
+            if (hipStreamSynchronize(s) != hipSuccess) { rc = SPHFILT_EDEVICE; break; }
+            free_work(b);
+            b->fused = fz;
+        }
+        for (int split = 0; split <= 1 && !rc; ++split) {
+            for (int wpc = -1; wpc <= b->max_wpc && !rc; ++wpc) {
+                if (wpc == 0) continue;
+                b->split = split;
+                b->wpc = wpc;
+                double us = 0;
+                rc = time_schedule(b, bufs, s, 5, &us);
+                if (!rc && us < best) {
+                    best = us;
+                    best_split = split;
+                    best_wpc = wpc;
+                    best_fused = fz;
+                }
             }
         }
     }
@@ -471,10 +536,15 @@ int tune(sphfilt_batch b, const char *cache_path)
     if (s) (void)hipStreamDestroy(s);
     (void)hipFree(scratch);
     if (rc) return rc;
+    if (b->fused != best_fused) {
+        free_work(b);
+        b->fused = best_fused;
+    }
     b->split = best_split;
     b->wpc = best_wpc;
     b->tuned_us = best;
-    if (cache_path && !cache_store(cache_path, hex64(b->signature), b->arch, best_split, best_wpc, best))
+    if (cache_path && !cache_store(cache_path, hex64(b->signature), b->arch, best_split, best_wpc,
+                                   best_fused, best))
         return SPHFILT_EINVAL;
     return SPHFILT_OK;
 }
@@ -504,6 +574,7 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
     try {
         std::vector<ThetaItem> all_th;
         std::vector<PhiItem> all_ph;
+        std::vector<double> all_fc;
         std::vector<BatchPatchDev> pdev;
         int shell_base = 0;
         for (int p = 0; p < n_patches; ++p) {
@@ -522,6 +593,10 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
             shell_base += d.n_fields * d.n_r;
             all_th.insert(all_th.end(), h.tables.theta.begin(), h.tables.theta.end());
             all_ph.insert(all_ph.end(), h.tables.phi.begin(), h.tables.phi.end());
+            h.phi_rest_off = (int)all_ph.size();
+            all_ph.insert(all_ph.end(), h.tables.phi_rest.begin(), h.tables.phi_rest.end());
+            h.fc_off = (int)all_fc.size();
+            all_fc.insert(all_fc.end(), h.tables.fused_c.begin(), h.tables.fused_c.end());
             b->patches.push_back(std::move(h));
         }
         th = (long long)all_th.size();
@@ -560,6 +635,7 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
         }
         if (!rc) rc = upload(&b->d_th, all_th);
         if (!rc) rc = upload(&b->d_ph, all_ph);
+        if (!rc) rc = upload(&b->d_fc, all_fc);
         if (!rc) rc = upload(&b->d_patches, pdev);
         if (!rc) rc = upload(&b->d_eneg, exp_table());
         if (!rc) rc = upload(&b->d_counters, std::vector<int>((size_t)std::max(1, b->n_shells_total), 0));
@@ -573,10 +649,11 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
     (void)th;
     (void)ph;
     if (!rc && tune_cache_path) {
-        int split = 0, wpc = 0;
-        if (cache_lookup(tune_cache_path, hex64(b->signature), &split, &wpc)) {
+        int split = 0, wpc = 0, fused = 1;
+        if (cache_lookup(tune_cache_path, hex64(b->signature), &split, &wpc, &fused)) {
             b->split = split;
             b->wpc = wpc;
+            b->fused = fused;
         } else {
             rc = tune(b, tune_cache_path);
         }
@@ -661,9 +738,33 @@ int sphfilt_batch_stats(sphfilt_batch batch, sphfilt_stats *out)
         const long long *src = (const long long *)&s;
         for (size_t i = 0; i < sizeof(s) / sizeof(long long); ++i) dst[i] += src[i];
     }
-    // the batch runs every patch in two passes
-    out->shells_fused = 0;
-    out->bytes_fused_inplace = 0;
+    if (!batch->fused) {
+        out->shells_fused = 0;
+        out->bytes_fused_inplace = out->bytes_forward_inplace;
+    }
+    return SPHFILT_OK;
+}
+
+int sphfilt_batch_set_fused(sphfilt_batch batch, int enable)
+{
+    if (!batch || (enable != 0 && enable != 1)) return SPHFILT_EINVAL;
+    if (batch->fused == enable) return SPHFILT_OK;
+    DeviceGuard g(batch->device);
+    if (!g.ok) return SPHFILT_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return SPHFILT_EDEVICE;
+    free_work(batch);
+    batch->fused = enable;
+    return SPHFILT_OK;
+}
+
+int sphfilt_batch_get_fused(sphfilt_batch batch, int *enable, int *shells_fused)
+{
+    if (!batch) return SPHFILT_EINVAL;
+    int n = 0;
+    for (const PatchHost &p : batch->patches)
+        if (patch_fused(batch, p)) n += p.tables.n_fused;
+    if (enable) *enable = batch->fused;
+    if (shells_fused) *shells_fused = n;
     return SPHFILT_OK;
 }
 

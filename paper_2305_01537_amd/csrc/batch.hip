@@ -16,14 +16,19 @@
 // additionally turns a logic error into a flagged error instead of a hang.
 //
 // The per-line work is done by the same workers as the per-plan kernels
-// (line_filter.h), so a batch and per-patch plans give bit-identical results.
+// (line_filter.h).  Patches whose shells fit in LDS (n_phi = 2 n_theta <=
+// 128) run their theta-filtered shells as fused items (both passes, one HBM
+// round trip, as a plan does) and the rings of their other shells in the
+// first pass: such a patch has no second-pass work.
 #include "batch_internal.h"
 #include "line_filter.h"
 
 namespace sphfilt {
 
-// LDS of the largest worker: max over N of lines_per_256<N> * line_lds.
-constexpr int kBatchLds = 4640;
+// LDS of the largest worker: the line scratch of every theta/phi group
+// (max over N of lines_per_256<N> * line_lds = 4640 doubles) and the staged
+// shells of the fused worker (ShellShape<128>::lds).
+constexpr int kBatchLds = ShellShape<128>::lds > 4640 ? ShellShape<128>::lds : 4640;
 
 // Hybrid lines in a batch decide from their data; decisions are not recorded.
 __device__ __forceinline__ HybridArgs batch_hybrid(const BatchPatchDev &pd)
@@ -52,6 +57,21 @@ __device__ __forceinline__ void phi_item(const BatchWork &w, const BatchPatchDev
                                      eneg, lds, etab, flags, batch_hybrid(pd), lane);
 }
 
+template <int N, bool HYB>
+__device__ __forceinline__ void fused_item(const BatchWork &w, const BatchPatchDev &pd,
+                                           const double *src, double *dst, const ThetaItem *th,
+                                           const double *fc, const double *eneg, double *lds,
+                                           double *etab, int *flags, int lane)
+{
+    const HybridArgs h = batch_hybrid(pd);
+    if (w.tile)
+        shell_block<N, true, HYB>(src, dst, th + w.first, fc + w.aux, w.n_valid, pd.tw_phi, eneg,
+                                  lds, etab, flags, h, h, lane);
+    else
+        shell_block<N, false, HYB>(src, dst, th + w.first, fc + w.aux, w.n_valid, pd.tw_phi, eneg,
+                                   lds, etab, flags, h, h, lane);
+}
+
 struct BatchArgs {
     const BatchWork *work;
     int n_work;
@@ -60,6 +80,7 @@ struct BatchArgs {
     double *const *outs;
     const ThetaItem *th;
     const PhiItem *ph;
+    const double *fc;
     const int *shells;
     int *counters;
     const int *need;
@@ -109,6 +130,12 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
         case 64: theta_item<64, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
         case 128: theta_item<128, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
         default: theta_item<256, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+        }
+    } else if (w.pass == 2) {
+        switch (pd.n_phi) {
+        case 32: fused_item<32, HYB>(w, pd, src, dst, a.th, a.fc, a.eneg, lds, etab, flags, lane); break;
+        case 64: fused_item<64, HYB>(w, pd, src, dst, a.th, a.fc, a.eneg, lds, etab, flags, lane); break;
+        default: fused_item<128, HYB>(w, pd, src, dst, a.th, a.fc, a.eneg, lds, etab, flags, lane); break;
         }
     } else {
         switch (pd.n_phi) {
@@ -206,12 +233,12 @@ hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n
 
 hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const BatchPatchDev *patches,
                         const double *const *ins, double *const *outs, const ThetaItem *th,
-                        const PhiItem *ph, const int *shells, int *counters, const int *need,
-                        int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
-                        int hybrid, hipStream_t s)
+                        const PhiItem *ph, const double *fc, const int *shells, int *counters,
+                        const int *need, int *ticket, int *error, const double *eneg, int use_deps,
+                        int spin_limit, int hybrid, hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
-    const BatchArgs a{work, n_work, patches, ins, outs, th, ph, shells, counters,
+    const BatchArgs a{work, n_work, patches, ins, outs, th, ph, fc, shells, counters,
                       need, ticket, error, eneg, use_deps, spin_limit};
     if (grid <= 0) {
         if (hybrid) batch_kernel_oneshot<true><<<n_work, 256, 0, s>>>(a);

@@ -8,7 +8,10 @@ namespace sphfilt {
 
 // One work item of the persistent batch kernel.
 //   pass      0: theta group (n_valid shells x one meridian tile);
-//             1: phi group (n_valid ring pairs).
+//             1: phi group (n_valid ring pairs);
+//             2: fused shells (n_valid whole shells, both passes; tile = 1
+//                for the adjoint order, aux = index of the first shell's
+//                ring cutoffs in the batch's fused cutoff array).
 //   second    0: first pass (reads `in`, writes `out`, signals its shells);
 //             1: second pass (works in place on `out`, waits for its shells).
 //   first     index of the first item in the batch's concatenated theta or
@@ -25,6 +28,8 @@ struct BatchWork {
     int16_t tile;
     int32_t shell_off;
     int32_t n_shells;
+    int32_t aux;
+    int32_t pad;
 };
 
 // Per-patch constants of the batch kernel.
@@ -45,7 +50,8 @@ hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n
 // per item.
 hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const BatchPatchDev *patches,
                         const double *const *ins, double *const *outs, const ThetaItem *th,
-                        const PhiItem *ph, const int *shells, int *counters, const int *need,
+                        const PhiItem *ph, const double *fc, const int *shells, int *counters,
+                        const int *need,
                         int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
                         int hybrid, hipStream_t s);
 // Resident 256-lane workgroups of the persistent batch kernel per compute

@@ -332,6 +332,18 @@ class Batch:
         _lib.check("sphfilt_batch_stats", self._lib.sphfilt_batch_stats(self._h, ctypes.byref(st)))
         return st.as_dict()
 
+    def set_fused(self, enable: bool):
+        """Fused items for patches whose shells fit in LDS (the default), or
+        every patch in two passes; see sphfilt_batch_set_fused."""
+        _lib.check("sphfilt_batch_set_fused", self._lib.sphfilt_batch_set_fused(self._h, int(bool(enable))))
+
+    def get_fused(self):
+        """(enabled, number of shells fused)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _lib.check("sphfilt_batch_get_fused",
+                   self._lib.sphfilt_batch_get_fused(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return bool(a.value), b.value
+
 
 def lib():
     return _lib.load()

@@ -179,6 +179,7 @@ def test_hybrid_batch_equals_plans(torch_gpu):
         plan.set_fused(False)       # the batch runs every patch in two passes
         refs.append(plan.apply(torch.from_numpy(p["x"]).cuda()).cpu().numpy())
     batch = Batch(pats)
+    batch.set_fused(False)          # two passes, bitwise the two-pass plans
     for split in (0, 1):
         for wpc in (-1, 1):
             batch.set_schedule(split, wpc)
@@ -188,3 +189,14 @@ def test_hybrid_batch_equals_plans(torch_gpu):
             for y, r in zip(ys, refs):
                 ok = bool(np.array_equal(y.cpu().numpy(), r))
                 assert ok, (split, wpc)
+    # fused items (every patch here has n_phi = 2 n_theta <= 128): the hybrid
+    # decisions are taken on the same data, the results agree to rounding
+    batch.set_fused(True)
+    assert batch.get_fused()[1] > 0
+    ys = batch.apply([torch.from_numpy(p["x"]).cuda() for p in pats])
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    for y, r, p in zip(ys, refs, pats):
+        assert rel(y.cpu().numpy(), r) <= 1e-14
+        ref_o = oracle.forward(p["x"], parity=p["parity"], L=p["L"], kind=p["kind"])
+        assert rel(y.cpu().numpy(), ref_o) <= TOL
