@@ -312,6 +312,11 @@ int sphfilt_batch_tune(sphfilt_batch batch, const char *tune_cache_path);
  *   split              0: one persistent kernel; second-pass items wait on
  *                      per-shell counters of the first pass.  1: two
  *                      persistent kernels, first pass then second pass.
+ *                      2: as 1, and the second-pass items whose shells no
+ *                      first-pass item writes (in place: the rings of
+ *                      theta-idle shells) run on a parallel branch of the
+ *                      graph, on a stream of the batch, alongside the first
+ *                      pass.
  *   workgroups_per_cu  -1: one workgroup per work item (each takes one item
  *                      and exits).  k > 0: a persistent grid of k workgroups
  *                      per compute unit looping over items; 0 = the most

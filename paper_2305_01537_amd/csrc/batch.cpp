@@ -46,6 +46,8 @@ struct PatchHost {
 struct ModeWork {
     bool built = false;
     int n_work = 0, n_first = 0;
+    int n_indep = 0;        // second-pass items at [n_first, n_first + n_indep) touch no
+                            // shell a first-pass item writes
     BatchWork *d_work = nullptr;
     int *d_shells = nullptr;
     int *d_need = nullptr;
@@ -89,6 +91,8 @@ struct sphfilt_batch_s {
     double tuned_us = -1.0;
     uint64_t clock = 0;
     hipStream_t capture_stream = nullptr;
+    hipStream_t side_stream = nullptr;    // parallel branch of split = 2 graphs
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -150,7 +154,7 @@ bool cache_lookup(const char *path, const std::string &sig, int *split, int *wpc
         *wpc = std::atoi(line.c_str() + b + 7);
         const size_t c = line.find("\"fused\": ");
         *fused = c == std::string::npos ? 1 : std::atoi(line.c_str() + c + 9);
-        return (*split == 0 || *split == 1) && *wpc >= -1 && *wpc <= 64 && (*fused == 0 || *fused == 1);
+        return *split >= 0 && *split <= 2 && *wpc >= -1 && *wpc <= 64 && (*fused == 0 || *fused == 1);
     }
     return false;
 }
@@ -277,18 +281,32 @@ int build_mode(sphfilt_batch b, int mode)
             add_pass(b, p, !adjoint, !inplace, false, &work, &shells);
     }
     const int n_first = (int)work.size();
+    std::vector<BatchWork> second;
     for (int p = 0; p < (int)b->patches.size(); ++p)
         if (!patch_fused(b, b->patches[(size_t)p]))
-            add_pass(b, p, adjoint, false, true, &work, &shells);
+            add_pass(b, p, adjoint, false, true, &second, &shells);
     std::vector<int> need((size_t)std::max(1, b->n_shells_total), 0);
     for (int k = 0; k < n_first; ++k)
         for (int i = 0; i < work[(size_t)k].n_shells; ++i) ++need[(size_t)shells[(size_t)(work[(size_t)k].shell_off + i)]];
+    // second-pass items whose shells no first-pass item writes (in place: the
+    // rings of theta-idle shells in the forward order) come first: they need
+    // not wait, and split = 2 runs them on a parallel branch
+    auto independent = [&](const BatchWork &w) {
+        for (int i = 0; i < w.n_shells; ++i)
+            if (need[(size_t)shells[(size_t)(w.shell_off + i)]] > 0) return false;
+        return true;
+    };
+    std::stable_partition(second.begin(), second.end(), independent);
+    int n_indep = 0;
+    while (n_indep < (int)second.size() && independent(second[(size_t)n_indep])) ++n_indep;
+    work.insert(work.end(), second.begin(), second.end());
     int rc = upload(&m.d_work, work);
     if (!rc) rc = upload(&m.d_shells, shells);
     if (!rc) rc = upload(&m.d_need, need);
     if (rc) return rc;
     m.n_work = (int)work.size();
     m.n_first = n_first;
+    m.n_indep = n_indep;
     m.built = true;
     return SPHFILT_OK;
 }
@@ -314,9 +332,30 @@ int record(sphfilt_batch b, const ModeWork &m, const GraphEntry &g, hipStream_t 
 {
     const int wpc = effective_wpc(b, g.wpc);
     const int grid = wpc < 0 ? 0 : wpc * b->n_cu;
-    hipError_t e = launch_batch_reset(b->d_counters, b->n_shells_total, b->d_tickets, 2, b->d_error, s);
+    hipError_t e = launch_batch_reset(b->d_counters, b->n_shells_total, b->d_tickets, 3, b->d_error, s);
     if (e != hipSuccess) return SPHFILT_EDEVICE;
-    if (g.split) {
+    if (g.split == 2 && m.n_indep > 0) {
+        // fork: the independent second-pass items on the side stream, the
+        // first pass and then the dependent second-pass items here; join
+        const int dep0 = m.n_first + m.n_indep;
+        e = hipEventRecord(b->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->side_stream, b->fork, 0);
+        if (e == hipSuccess)
+            e = launch_batch(grid, m.d_work + m.n_first, m.n_indep, b->d_patches, g.d_ins, g.d_outs,
+                             b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
+                             b->d_tickets + 2, b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid,
+                             b->side_stream);
+        if (e == hipSuccess)
+            e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th,
+                             b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets,
+                             b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid, s);
+        if (e == hipSuccess)
+            e = launch_batch(grid, m.d_work + dep0, m.n_work - dep0, b->d_patches, g.d_ins, g.d_outs,
+                             b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
+                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid, s);
+        if (e == hipSuccess) e = hipEventRecord(b->join, b->side_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join, 0);
+    } else if (g.split) {
         e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
                          b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg,
                          0, kSpinLimit, b->hybrid, s);
@@ -405,6 +444,9 @@ void free_batch(sphfilt_batch b)
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
 }
 
 int check_pointers(sphfilt_batch b, const double *const *ins, double *const *outs, bool *inplace)
@@ -507,7 +549,7 @@ int tune(sphfilt_batch b, const char *cache_path)
             free_work(b);
             b->fused = fz;
         }
-        for (int split = 0; split <= 1 && !rc; ++split) {
+        for (int split = 0; split <= 2 && !rc; ++split) {
             for (int wpc = -1; wpc <= b->max_wpc && !rc; ++wpc) {
                 if (wpc == 0) continue;
                 b->split = split;
@@ -639,9 +681,12 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
         if (!rc) rc = upload(&b->d_patches, pdev);
         if (!rc) rc = upload(&b->d_eneg, exp_table());
         if (!rc) rc = upload(&b->d_counters, std::vector<int>((size_t)std::max(1, b->n_shells_total), 0));
-        if (!rc) rc = upload(&b->d_tickets, std::vector<int>(2, 0));
+        if (!rc) rc = upload(&b->d_tickets, std::vector<int>(3, 0));
         if (!rc) rc = upload(&b->d_error, std::vector<int>(1, 0));
-        if (!rc && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        if (!rc && (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess ||
+                    hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking) != hipSuccess ||
+                    hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+                    hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess))
             rc = SPHFILT_EDEVICE;
     } catch (const std::bad_alloc &) {
         rc = SPHFILT_ENOMEM;
@@ -698,7 +743,7 @@ int sphfilt_batch_tune(sphfilt_batch batch, const char *tune_cache_path)
 
 int sphfilt_batch_set_schedule(sphfilt_batch batch, int split, int workgroups_per_cu)
 {
-    if (!batch || (split != 0 && split != 1) || workgroups_per_cu < -1 ||
+    if (!batch || split < 0 || split > 2 || workgroups_per_cu < -1 ||
         workgroups_per_cu > batch->max_wpc)
         return SPHFILT_EINVAL;
     batch->split = split;

@@ -172,8 +172,9 @@ __device__ __forceinline__ int next_ticket(int *ticket, int *cur)
     return k;
 }
 
-// One-shot form: a workgroup takes one ticket, runs that item and exits; the
-// grid has one workgroup per item.
+// One-shot form: the grid has one workgroup per item.  With waits between
+// items a workgroup takes a ticket (so that every awaited item is held by a
+// running workgroup); without, it runs item blockIdx.x and saves the atomic.
 template <bool HYB>
 __global__ __launch_bounds__(256) void batch_kernel_oneshot(BatchArgs a)
 {
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(256) void batch_kernel_oneshot(BatchArgs a)
     __shared__ double etab[129];
     __shared__ int flags[64];
     __shared__ int cur;
-    const int k = next_ticket(a.ticket, &cur);
+    const int k = a.use_deps ? next_ticket(a.ticket, &cur) : (int)blockIdx.x;
     if (k < a.n_work) run_item<HYB>(a, k, threadIdx.x, lds, etab, flags);
 }
 

@@ -80,7 +80,7 @@ def test_batch_equals_plans_every_schedule(torch_gpu, adjoint, inplace):
     ref = plan_outputs(torch, patches, adjoint, inplace)
     batch = Batch(patches)
     batch.set_fused(False)
-    for split in (0, 1):
+    for split in (0, 1, 2):
         for wpc in (-1, 1, 0):
             batch.set_schedule(split, wpc)
             xs = [torch.from_numpy(p["x"]).cuda() for p in patches]
@@ -94,13 +94,17 @@ def test_batch_equals_plans_every_schedule(torch_gpu, adjoint, inplace):
     batch.close()
 
 
-def test_batch_graph_replays_see_fresh_data(torch_gpu):
+@pytest.mark.parametrize("split,wpc,inplace", [(0, -1, False), (2, -1, True), (2, 1, True)])
+def test_batch_graph_replays_see_fresh_data(torch_gpu, split, wpc, inplace):
+    """Each call replays the cached graph (split = 2 in place: with its parallel
+    branch) on new values written into the same buffers."""
     torch = torch_gpu
     from paper_2305_01537_amd.filter import Batch
     patches = mixed_patches(43)
     batch = Batch(patches)
+    batch.set_schedule(split, wpc)
     xs = [torch.from_numpy(p["x"]).cuda() for p in patches]
-    outs = [torch.empty_like(x) for x in xs]
+    outs = xs if inplace else [torch.empty_like(x) for x in xs]
     rng = np.random.default_rng(44)
     for rep in range(4):
         # new values in the same buffers between replays, with eager work and syncs in between
@@ -108,11 +112,12 @@ def test_batch_graph_replays_see_fresh_data(torch_gpu):
             p["x"] = rng.standard_normal(p["x"].shape)
             x.copy_(torch.from_numpy(p["x"]))
         torch.cuda.synchronize()
+        print(f"[gpu] replay split={split} wpc={wpc} inplace={inplace} rep={rep}", flush=True)
         batch.apply(xs, outs=outs)
         torch.cuda.synchronize()
         # fused plans as the reference (the batch fuses by default): equal to
         # rounding, while a replay on stale data would be off by O(1)
-        ref = plan_outputs(torch, patches, False, False, fused=True)
+        ref = plan_outputs(torch, patches, False, inplace, fused=True)
         for i, (y, r) in enumerate(zip(outs, ref)):
             assert close(y.cpu().numpy(), r), (rep, i)
     assert batch.status() == 0
@@ -162,6 +167,19 @@ def test_batch_tuner_and_cache(torch_gpu, tmp_path):
         b.close()
 
 
+def test_batch_schedule_values(torch_gpu):
+    from paper_2305_01537_amd.filter import Batch, SphfiltError
+    batch = Batch(mixed_patches()[:3])
+    for split in (0, 1, 2):
+        batch.set_schedule(split, -1)
+        assert batch.get_schedule()["split"] == split
+    with pytest.raises(SphfiltError):
+        batch.set_schedule(3, -1)
+    with pytest.raises(SphfiltError):
+        batch.set_schedule(0, -2)
+    batch.close()
+
+
 def test_batch_rejects_overlaps(torch_gpu):
     torch = torch_gpu
     from paper_2305_01537_amd.filter import Batch, SphfiltError
@@ -209,7 +227,7 @@ def test_fused_batch_matches_fused_plans_every_schedule(torch_gpu, adjoint, inpl
     assert enabled and n_fused == st["shells_fused"] > 0
     assert st["bytes_fused_inplace"] < st["bytes_forward_inplace"]
     first = None
-    for split in (0, 1):
+    for split in (0, 1, 2):
         for wpc in (-1, 1, 0):
             batch.set_schedule(split, wpc)
             xs = [torch.from_numpy(p["x"]).cuda() for p in patches]

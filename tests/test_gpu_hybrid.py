@@ -180,7 +180,7 @@ def test_hybrid_batch_equals_plans(torch_gpu):
         refs.append(plan.apply(torch.from_numpy(p["x"]).cuda()).cpu().numpy())
     batch = Batch(pats)
     batch.set_fused(False)          # two passes, bitwise the two-pass plans
-    for split in (0, 1):
+    for split in (0, 1, 2):
         for wpc in (-1, 1):
             batch.set_schedule(split, wpc)
             ys = batch.apply([torch.from_numpy(p["x"]).cuda() for p in pats])
