@@ -44,8 +44,8 @@ struct DeviceTables {
 
 // A second stream of the plan, for ring pairs that do not depend on the theta
 // pass; fork and join events tie it to the caller's stream.  Created with the
-// plan when its lists allow overlap (so that no stream is created inside a
-// caller's graph capture), else on first use; the mutex covers the
+// plan when its lists allow overlap, so that no call creates a stream (a call
+// may be inside a caller's graph capture); the mutex covers the
 // fork-launch-join sequence, so that each call's waits refer to its own event
 // records.
 struct SideStream {
@@ -145,7 +145,7 @@ int apply_fused(sphfilt_plan p, bool adjoint, const double *in, double *out, con
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
 
-bool side_ready(SideStream &ss)
+bool side_create(SideStream &ss)
 {
     if (ss.state == 0) {
         ss.state = -1;
@@ -189,13 +189,13 @@ bool overlap_pays(sphfilt_plan p)
 // depend on it, so they run on the side stream while the caller's stream runs
 // the theta pass and the rings of the theta-filtered shells (in the call's
 // order); the caller's stream then waits for the side stream.  Returns
-// SPHFILT_EUNSUPPORTED when the side stream cannot be created (the caller
-// then runs two passes).
+// SPHFILT_EUNSUPPORTED when the plan has no side stream (the caller then runs
+// two passes).
 int apply_overlap(sphfilt_plan p, bool adjoint, double *x, const Decisions &d, hipStream_t s)
 {
     const HostTables &t = p->host;
     std::lock_guard<std::mutex> lock(p->side.m);
-    if (!side_ready(p->side)) return SPHFILT_EUNSUPPORTED;
+    if (p->side.state != 1) return SPHFILT_EUNSUPPORTED;
     HybridArgs ht = p->hybrid, hp = p->hybrid;
     ht.replay = hp.replay = d.replay;
     ht.dec = d.theta;
@@ -309,7 +309,7 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
     }
     const HostTables &t = p->host;
     if (!rc && t.n_fused == 0 && t.theta_active > 0 && t.phi_rest_active > 0 &&
-        !side_ready(p->side))
+        !side_create(p->side))
         rc = SPHFILT_EDEVICE;
     if (rc) {
         side_destroy(p->side);
