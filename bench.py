@@ -243,6 +243,34 @@ def bench_grmhd(torch, steps, stream):
     return out
 
 
+def bench_chain(torch, steps, stream):
+    """Differentiation on the chain workload (24 x 128 x 64 x 128, cal-L = 3):
+    y_{k+1} = tanh(F y_k), K = 8, loss sum (y_K - t)^2, forward and backward
+    through the adjoint filter, with and without checkpointing.  Reported per
+    step and per filter call (checkpointed: 8 forward, 8 recomputed forward
+    and 8 adjoint calls; plain: 8 forward and 8 adjoint)."""
+    from paper_2305_01537_amd import synth
+    from paper_2305_01537_amd.autograd import filter_chain
+    from paper_2305_01537_amd.filter import Plan
+    w = synth.workload("chain")
+    F, R, T, P = w.shape
+    plan = Plan(R, T, P, F, parity=w.parity, L=w.L, rho=w.rho)
+    x = torch.from_numpy(w.x).cuda()
+    t = torch.from_numpy(w.target).cuda()
+    out = {"workload": f"chain: {F} x {R} x {T} x {P}, K = 8, tanh between filters"}
+    for ck in (True, False):
+        def step(_):
+            xv = x.detach().requires_grad_(True)
+            y = filter_chain(xv, plan, 8, checkpoint=ck)
+            ((y - t) ** 2).sum().backward()
+        ms = time_loop(torch, step, [None], steps, 2, stream)
+        calls = 24 if ck else 16
+        out["checkpointed" if ck else "plain"] = {"step_ms": ms, "filter_calls": calls,
+                                                  "ms_per_filter_call_upper_bound": ms / calls}
+    plan.close()
+    return out
+
+
 def bench_short_lines(torch, steps, stream):
     """Dense cutoff (every line filtered) on grids with short lines,
     n_phi = 2 n_theta = 32, 64, 128, 24 fields and about 800 MB per buffer
@@ -392,6 +420,9 @@ def main():
         log("timing the grmhd grid (fused shells)")
         extra["grmhd"] = bench_grmhd(torch, max(10, args.steps // 2), stream)
         log(f"grmhd: {extra['grmhd']}")
+        log("timing the differentiation chain")
+        extra["chain"] = bench_chain(torch, max(5, args.steps // 20), stream)
+        log(f"chain: {extra['chain']}")
         log("timing the 64-patch batch")
         extra["patches"] = bench_patches(torch, max(10, args.steps // 2), stream)
         log(f"patches: {extra['patches']}")
