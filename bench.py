@@ -271,6 +271,31 @@ def bench_chain(torch, steps, stream):
     return out
 
 
+def bench_hybrid(torch, w, bufs, steps, stream):
+    """The share with the paper's split of fields: 8 matter fields with the
+    hybrid exponential/Gaussian switch at cal-L = 12, 16 metric fields
+    exponential at cal-L = 3; forward in place, and with the decisions
+    recorded (apply_ex) as the autograd forward does."""
+    import numpy as np
+    from paper_2305_01537_amd.filter import Plan
+    F, R, T, P = w.shape
+    kind = np.zeros(F, dtype=np.int32)
+    kind[:8] = 3
+    L = np.where(kind == 3, 12.0, 3.0)
+    plan = Plan(R, T, P, F, parity=w.parity, L=L, rho=w.rho, kind=kind)
+    st = plan.stats()
+    ms = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 3, stream)
+    th, ph = plan.decision_buffers()
+    ms_rec = time_loop(torch, lambda b: plan.apply_ex(b, out=b, theta_dec=th, phi_dec=ph), bufs,
+                       steps, 3, stream)
+    plan.close()
+    return {"workload": "share, fields 0..7 hybrid (cal-L 12), 8..23 exponential (cal-L 3)",
+            "forward_ms": ms, "forward_recording_ms": ms_rec,
+            "points_per_s": st["n_points"] / (ms * 1e-3),
+            "GBps": st["bytes_forward_inplace"] / (ms * 1e-3) / 1e9,
+            "algorithmic_bytes": st["bytes_forward_inplace"]}
+
+
 def bench_short_lines(torch, steps, stream):
     """Dense cutoff (every line filtered) on grids with short lines,
     n_phi = 2 n_theta = 32, 64, 128, 24 fields and about 800 MB per buffer
@@ -426,6 +451,9 @@ def main():
         log("timing the 64-patch batch")
         extra["patches"] = bench_patches(torch, max(10, args.steps // 2), stream)
         log(f"patches: {extra['patches']}")
+        log("timing the hybrid filter on the share")
+        extra["hybrid"] = bench_hybrid(torch, w, bufs, max(10, args.steps // 4), stream)
+        log(f"hybrid: {extra['hybrid']}")
         # streaming reference: torch's own in-place elementwise kernel on the same buffers
         ms_ref = time_loop(torch, lambda b: b.mul_(1.0), bufs, max(5, args.steps // 2), 2, stream)
         extra["stream_reference_GBps"] = 16 * points / (ms_ref * 1e-3) / 1e9

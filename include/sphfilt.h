@@ -252,7 +252,8 @@ int sphfilt_plan_get_overlap(sphfilt_plan plan, int *mode);
  * Batched filter: many uneven spherical patches in one launch.
  *
  * Each patch is filtered exactly as by its own plan (same operator, same
- * per-line arithmetic, so bit-identical results); the batch schedules every
+ * per-line arithmetic: bit-identical results to a two-pass plan without
+ * hybrid fields, equal to rounding otherwise); the batch schedules every
  * patch's theta groups and ring-pair groups as items of one persistent
  * kernel, replayed from a captured HIP graph.  This is the GPU counterpart of
  * the paper's OpenMP loop over many line transforms on one rank (Sec. II.C).

@@ -25,10 +25,18 @@
 
 namespace sphfilt {
 
-// LDS of the largest worker: the line scratch of every theta/phi group
-// (max over N of lines_per_256<N> * line_lds = 4640 doubles) and the staged
-// shells of the fused worker (ShellShape<128>::lds).
-constexpr int kBatchLds = ShellShape<128>::lds > 4640 ? ShellShape<128>::lds : 4640;
+// LDS of the largest worker: the staged shells of the fused worker
+// (ShellShape<128>::lds), which also covers the line scratch of every
+// theta/phi group, hybrid spectra included.
+constexpr int kBatchLds = ShellShape<128>::lds;
+template <int N>
+constexpr bool batch_lds_fits()
+{
+    return kBatchLds >= lines_per_256<N>() * line_stride<Split<N>::N1, Split<N>::N2, true>();
+}
+static_assert(batch_lds_fits<32>() && batch_lds_fits<64>() && batch_lds_fits<128>() &&
+                  batch_lds_fits<256>(),
+              "batch LDS holds every worker's line scratch");
 
 // Hybrid lines in a batch decide from their data; decisions are not recorded.
 __device__ __forceinline__ HybridArgs batch_hybrid(const BatchPatchDev &pd)
@@ -175,8 +183,11 @@ __device__ __forceinline__ int next_ticket(int *ticket, int *cur)
 // One-shot form: the grid has one workgroup per item.  With waits between
 // items a workgroup takes a ticket (so that every awaited item is held by a
 // running workgroup); without, it runs item blockIdx.x and saves the atomic.
+// The hybrid form needs a little more than 256 registers: two waves per SIMD
+// with a small spill (128 bytes per lane) beat one wave without (the hybrid
+// 64-patch batch: 2.05 against 2.64 ms).
 template <bool HYB>
-__global__ __launch_bounds__(256) void batch_kernel_oneshot(BatchArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HYB ? 2 : 1))) void batch_kernel_oneshot(BatchArgs a)
 {
     __shared__ double lds[kBatchLds];
     __shared__ double etab[129];
@@ -191,7 +202,7 @@ __global__ __launch_bounds__(256) void batch_kernel_oneshot(BatchArgs a)
 // so that per-lane index math is recomputed rather than kept live across
 // items (it would otherwise not fit in 256 registers).  The hybrid form, with
 // the detector and the mixed-pair mask, needs more than 256 registers; it runs
-// one wave per SIMD instead of spilling to scratch.
+// one wave per SIMD (at two it would spill 240 bytes per lane and lose a third).
 template <bool HYB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HYB ? 1 : 2))) void batch_kernel_persistent(
     BatchArgs a)

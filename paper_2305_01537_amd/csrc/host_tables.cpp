@@ -90,6 +90,18 @@ int validate(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
     return SPHFILT_OK;
 }
 
+// Items [0, k) of the first n are hybrid and the rest of them are not: k, or
+// n when hybrid items come later (then every item takes the hybrid kernel).
+template <typename T>
+static int hybrid_prefix(const std::vector<T> &items, int n)
+{
+    int k = 0;
+    while (k < n && (items[(size_t)k].flags & kKindMask) == SPHFILT_HYBRID) ++k;
+    for (int i = k; i < n; ++i)
+        if ((items[(size_t)i].flags & kKindMask) == SPHFILT_HYBRID) return n;
+    return k;
+}
+
 void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
                  const sphfilt_cutoff *cut, HostTables *h)
 {
@@ -97,7 +109,13 @@ void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parit
     std::vector<ThetaItem> tf, ta, ti;     // fused, other active, identity shells
     std::vector<PhiItem> pa, pi, ra, ri;   // all rings; rings of unfused shells
     std::vector<PhiItem> rings;
-    for (int f = 0; f < n_fields; ++f) {
+    // hybrid fields first: every list then starts with the hybrid items, which
+    // the hybrid-capable kernels take, and the plain kernels take the rest
+    std::vector<int> order;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int f = 0; f < n_fields; ++f)
+            if ((cut->kind && cut->kind[f] == SPHFILT_HYBRID) == (pass == 0)) order.push_back(f);
+    for (const int f : order) {
         const int kind = cut->kind ? cut->kind[f] : SPHFILT_EXP;
         const int base_flags = kind | (parity[f] < 0 ? kFlagOddParity : 0);
         const double L = cut->L[f];
@@ -146,6 +164,10 @@ void build_items(int n_r, int n_theta, int n_phi, int n_fields, const int *parit
     h->phi_rest_active = (int)ra.size();
     h->phi_rest = std::move(ra);
     h->phi_rest.insert(h->phi_rest.end(), ri.begin(), ri.end());
+    h->theta_hyb = hybrid_prefix(h->theta, h->theta_active);
+    h->phi_hyb = hybrid_prefix(h->phi, h->phi_active);
+    h->fused_hyb = hybrid_prefix(h->theta, h->n_fused);
+    h->phi_in_hyb = hybrid_prefix(h->phi_in, (int)h->phi_in.size());
 }
 
 HybridArgs hybrid_args(const sphfilt_cutoff *cut, int n_fields)

@@ -25,6 +25,10 @@ struct HostTables {
     std::vector<PhiItem> phi_rest;
     int phi_rest_active = 0;
     std::vector<PhiItem> phi_in;
+    // leading hybrid items of the active prefix of theta, of phi, of the fused
+    // shells and of phi_in (hybrid fields come first; a hybrid line is never
+    // identity, and the theta-idle shells of phi_rest are never hybrid)
+    int theta_hyb = 0, phi_hyb = 0, fused_hyb = 0, phi_in_hyb = 0;
 };
 
 bool fault(const char *what);

@@ -1,22 +1,28 @@
 // kernels.hip -- per-plan kernels of the double FFT filter (arXiv:2305.01537,
 // Sec. II.B) for gfx950, FP64: one launch per pass over a plan's item list.
 // The work of a workgroup is done by the workers in line_filter.h, which the
-// batched persistent kernel (batch.hip) shares, so a plan and a batch produce
-// bit-identical results for the same launch shape.
+// batched persistent kernel (batch.hip) shares: the same arithmetic per line
+// (bit for bit where the compiler contracts multiply-adds the same way in
+// both kernels, to rounding otherwise).
 #include "line_filter.h"
+
+// The hybrid-capable theta and phi kernels need a little more than 256
+// registers at N = 256: two waves per SIMD with a small spill (68-84 bytes per
+// lane) beat one wave without (the share with 8 hybrid fields: 0.81 against
+// 1.25 ms per forward filter).
 
 namespace sphfilt {
 
 // theta-pass: workgroup b handles shell group g = b / tiles (S = C / cp shells
 // of the item list) and meridian tile b % tiles.
 template <int N, int C, bool HYB>
-__global__ __launch_bounds__(C * Split<N>::N2) SPHFILT_OCCUPANCY void theta_kernel(
+__global__ __launch_bounds__(C * Split<N>::N2) __attribute__((amdgpu_waves_per_eu(HYB ? 2 : 1))) void theta_kernel(
     const double *in, double *out, const ThetaItem *__restrict__ items, int n_items, int cp_log2,
     int tiles, int n_theta, int n_phi, const Twiddle *__restrict__ tw,
     const double *__restrict__ eneg, HybridArgs h)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-    __shared__ double lds[C * line_lds<N1, N2>()];
+    __shared__ double lds[C * line_stride<N1, N2, HYB>()];
     __shared__ double etab[N / 2 + 1];
     __shared__ int flags[C];
     const int group = blockIdx.x / tiles, tile = blockIdx.x % tiles;
@@ -29,12 +35,12 @@ __global__ __launch_bounds__(C * Split<N>::N2) SPHFILT_OCCUPANCY void theta_kern
 
 // phi-pass: workgroup b handles ring pairs [b * LINES, b * LINES + LINES).
 template <int N, int LINES, bool HYB>
-__global__ __launch_bounds__(LINES * Split<N>::N2) SPHFILT_OCCUPANCY void phi_kernel(
+__global__ __launch_bounds__(LINES * Split<N>::N2) __attribute__((amdgpu_waves_per_eu(HYB ? 2 : 1))) void phi_kernel(
     const double *in, double *out, const PhiItem *__restrict__ items, int n_items, int n_theta,
     const Twiddle *__restrict__ tw, const double *__restrict__ eneg, HybridArgs h)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-    __shared__ double lds[LINES * line_lds<N1, N2>()];
+    __shared__ double lds[LINES * line_stride<N1, N2, HYB>()];
     __shared__ double etab[N / 2 + 1];
     __shared__ int flags[LINES];
     const int first = blockIdx.x * LINES;
@@ -56,7 +62,7 @@ __global__ __launch_bounds__(256) void shell_phi_kernel(
 {
     using S = ShellShape<N>;
     constexpr int LINES = 256 / Split<N>::N2;
-    static_assert(S::lds >= LINES * line_lds<Split<N>::N1, Split<N>::N2>(), "ring-pair scratch");
+    static_assert(S::lds >= LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>(), "ring-pair scratch");
     __shared__ double lds[S::lds];
     __shared__ double etab[N / 2 + 1];
     __shared__ int flags[LINES];

@@ -30,16 +30,6 @@ constexpr double kLog09 = -0.10536051565782630123;
 #ifndef SPHFILT_NT_STORE_PHI
 #define SPHFILT_NT_STORE_PHI 1
 #endif
-// Minimum waves per SIMD requested from the register allocator (0: compiler's
-// choice).  Bounds the VGPR count of the large-N kernels.
-#ifndef SPHFILT_WAVES
-#define SPHFILT_WAVES 0
-#endif
-#if SPHFILT_WAVES > 0
-#define SPHFILT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SPHFILT_WAVES)))
-#else
-#define SPHFILT_OCCUPANCY
-#endif
 
 __device__ __forceinline__ double ld_stream(const double *p)
 {
@@ -110,8 +100,10 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[N1], int t, int kind, doubl
 // and b) are (Z[q] + conj Z[-q]) / 2 and (Z[q] - conj Z[-q]) / 2i, so
 //   f_a A + i f_b B = (f_a + f_b)/2 Z[q] + (f_a - f_b)/2 conj Z[N - q].
 // Bin N - q lives on another lane: every lane publishes its bins through the
-// line's LDS region L (natural order, real then imaginary parts).  Lines with
-// ka == kb get plain f Z.  All lanes of the workgroup call this together.
+// line's LDS region P (2N doubles: real parts, then imaginary parts, natural
+// order), so one barrier serves both parts and each mode's factors are used
+// as soon as they are formed.  Lines with ka == kb get plain f Z.  All lanes
+// of the workgroup call this together.
 template <int N1, int N2>
 __device__ __forceinline__ double kind_mask(int kind, int qhat, int m, double g_exp,
                                             double inv_c1, const double *etab)
@@ -127,7 +119,7 @@ __device__ __forceinline__ double kind_mask(int kind, int qhat, int m, double g_
 
 template <int N1, int N2>
 __device__ __forceinline__ void apply_mask_pair(cplx (&v)[N1], int t, int ka, int kb, double c,
-                                                const double *etab, double *L)
+                                                const double *etab, double *P)
 {
     constexpr int N = N1 * N2;
     constexpr int R = N1 / N2;
@@ -135,40 +127,45 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[N1], int t, int ka, in
     const int m = c >= (double)N ? N : (int)floor(c);
     const double g_exp = exp((c - (double)m) - 1.0) * inv_n;
     const double inv_c1 = 1.0 / (c + 1.0);
-    static_for<0, 2>([&](auto part) {
-        constexpr bool im = decltype(part)::value == 1;
-        static_for<0, R>([&](auto rr) {
-            constexpr int r = decltype(rr)::value;
-            static_for<0, N2>([&](auto kk) {
-                constexpr int k2 = decltype(kk)::value;
-                L[t + N2 * r + N1 * k2] = im ? v[r * N2 + k2].im : v[r * N2 + k2].re;
-            });
+    static_for<0, R>([&](auto rr) {
+        constexpr int r = decltype(rr)::value;
+        static_for<0, N2>([&](auto kk) {
+            constexpr int k2 = decltype(kk)::value;
+            const int q = t + N2 * r + N1 * k2;
+            P[q] = v[r * N2 + k2].re;
+            P[N + q] = v[r * N2 + k2].im;
         });
-        __syncthreads();
-        static_for<0, R>([&](auto rr) {
-            constexpr int r = decltype(rr)::value;
-            static_for<0, N2>([&](auto kk) {
-                constexpr int k2 = decltype(kk)::value;
-                const int q = t + N2 * r + N1 * k2;
-                const int qhat = q <= N / 2 ? q : N - q;
-                const double fa = kind_mask<N1, N2>(ka, qhat, m, g_exp, inv_c1, etab);
-                const double fb = ka == kb ? fa : kind_mask<N1, N2>(kb, qhat, m, g_exp, inv_c1, etab);
-                const double alpha = 0.5 * (fa + fb), beta = 0.5 * (fa - fb);
-                const double partner = L[(N - q) & (N - 1)];
-                if constexpr (im)
-                    v[r * N2 + k2].im = alpha * v[r * N2 + k2].im - beta * partner;
-                else
-                    v[r * N2 + k2].re = alpha * v[r * N2 + k2].re + beta * partner;
-            });
-        });
-        __syncthreads();
     });
+    __syncthreads();
+    static_for<0, R>([&](auto rr) {
+        constexpr int r = decltype(rr)::value;
+        static_for<0, N2>([&](auto kk) {
+            constexpr int k2 = decltype(kk)::value;
+            const int q = t + N2 * r + N1 * k2;
+            const int qhat = q <= N / 2 ? q : N - q;
+            const double fa = kind_mask<N1, N2>(ka, qhat, m, g_exp, inv_c1, etab);
+            const double fb = ka == kb ? fa : kind_mask<N1, N2>(kb, qhat, m, g_exp, inv_c1, etab);
+            const double alpha = 0.5 * (fa + fb), beta = 0.5 * (fa - fb);
+            const int qp = (N - q) & (N - 1);
+            v[r * N2 + k2].re = alpha * v[r * N2 + k2].re + beta * P[qp];
+            v[r * N2 + k2].im = alpha * v[r * N2 + k2].im - beta * P[N + qp];
+        });
+    });
+    __syncthreads();
 }
 
 // LDS doubles per line: an N1 x (N2 + 1) padded tile plus one double, so that
 // consecutive lines start on different banks.
 template <int N1, int N2>
 constexpr int line_lds() { return N1 * (N2 + 1) + 1; }
+
+// LDS doubles per line of a kernel: the hybrid-capable variants also publish
+// a whole spectrum (2N doubles) for the two-kind mask.
+template <int N1, int N2, bool HYB>
+constexpr int line_stride()
+{
+    return HYB && 2 * N1 * N2 + 1 > line_lds<N1, N2>() ? 2 * N1 * N2 + 1 : line_lds<N1, N2>();
+}
 
 // Forward transpose: lane t holds Y[k1][t] in v[k1]; afterwards it holds
 // Y[t + N2 r][n2] in v[r * N2 + n2].  Real and imaginary parts go through LDS
@@ -438,7 +435,7 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
     // transform (the barriers are workgroup-wide) but their result is dropped;
     // they are copied exactly from `in`.  That only happens out of place.
     if (any_active) {
-        double *L = lds + p * line_lds<N1, N2>();
+        double *L = lds + p * line_stride<N1, N2, HYB>();
         const size_t dline = (size_t)it.shell * (size_t)half;
         int ka = it.flags & kKindMask, kb = ka;
         bool mixed = false;
@@ -503,7 +500,7 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
                       : cplx{0.0, 0.0};
     });
     if (any_active) {
-        double *L = lds + p * line_lds<N1, N2>();
+        double *L = lds + p * line_stride<N1, N2, HYB>();
         const size_t ring_b = (size_t)it.ring + (size_t)(n_theta - 1 - 2 * j);
         int ka = it.flags & kKindMask, kb = ka;
         bool mixed = false;
@@ -541,8 +538,9 @@ namespace sphfilt {
 // result back into the staged shells, filters them in the phi layout and
 // stores them with contiguous stores (the adjoint order runs the phi pass
 // first).  Lines are packed and filtered exactly as by theta_block (with
-// cols = n_phi/4) and phi_block, so the result is bitwise that of the two
-// passes.  The line filter's LDS scratch reuses the staging memory.
+// cols = n_phi/4) and phi_block, so the result is that of the two passes up
+// to rounding (the compiler may contract multiply-adds differently in a
+// different kernel).  The line filter's LDS scratch reuses the staging memory.
 // ---------------------------------------------------------------------------
 template <int N> struct ShellShape {
     static constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
@@ -553,7 +551,7 @@ template <int N> struct ShellShape {
     static constexpr int stride = (N / 2) * row + 16;    // doubles per staged shell
     static constexpr int lds = shells * stride;
     static_assert(lanes % N == 0, "a shell's lanes cover whole rows");
-    static_assert(lds >= (256 / N2) * line_lds<N1, N2>(), "scratch fits in the staging area");
+    static_assert(lds >= (256 / N2) * line_stride<N1, N2, true>(), "scratch fits in the staging area");
 };
 
 // Staging: lane l of a shell's lanes moves elements e = k * lanes + l,
@@ -656,7 +654,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
     double *sb_p = lds + up * S::stride;
 
     auto theta_filter = [&]() {
-        double *L = lds + pt * line_lds<N1, N2>();
+        double *L = lds + pt * line_stride<N1, N2, HYB>();
         int ka = it.flags & kKindMask, kb = ka;
         bool mixed = false;
         if constexpr (HYB) {
@@ -667,7 +665,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         filter_line<N1, N2, HYB>(v, tt, ka, kb, mixed, valid_t ? it.c : INFINITY, L, tw, etab);
     };
     auto phi_filter = [&]() {
-        double *L = lds + pp * line_lds<N1, N2>();
+        double *L = lds + pp * line_stride<N1, N2, HYB>();
         int ka = kind_p, kb = ka;
         bool mixed = false;
         if constexpr (HYB) {

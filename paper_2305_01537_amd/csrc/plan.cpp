@@ -92,23 +92,59 @@ struct Decisions {
     int replay = 0;
 };
 
+// Hybrid arguments of one launch: the decision buffer of its pass, and
+// `present` only for the launch over hybrid items (the hybrid-capable kernel
+// instance costs registers and occupancy the plain one does not).
+HybridArgs pass_args(const sphfilt_plan p, unsigned char *dec, const Decisions &d, bool hybrid)
+{
+    HybridArgs h = p->hybrid;
+    h.replay = d.replay;
+    h.dec = dec;
+    h.present = hybrid ? p->hybrid.present : 0;
+    return h;
+}
+
+// The theta pass (or the phi pass) over items [0, n) of a list whose first
+// n_hyb items are hybrid: those with the hybrid-capable kernel, the rest with
+// the plain one.
+hipError_t theta_split(sphfilt_plan p, const double *in, double *out, const ThetaItem *items, int n,
+                       int n_hyb, const Decisions &d, hipStream_t s)
+{
+    const int nh = n_hyb < n ? n_hyb : n;
+    hipError_t e = hipSuccess;
+    if (nh > 0)
+        e = launch_theta(2 * p->n_theta, p->theta_cols, in, out, items, nh, p->n_theta, p->n_phi,
+                         p->dev.tw_theta, p->dev.eneg, pass_args(p, d.theta, d, true), s);
+    if (e == hipSuccess && n > nh)
+        e = launch_theta(2 * p->n_theta, p->theta_cols, in, out, items + nh, n - nh, p->n_theta,
+                         p->n_phi, p->dev.tw_theta, p->dev.eneg, pass_args(p, d.theta, d, false), s);
+    return e;
+}
+
+hipError_t phi_split(sphfilt_plan p, const double *in, double *out, const PhiItem *items, int n,
+                     int n_hyb, const Decisions &d, hipStream_t s)
+{
+    const int nh = n_hyb < n ? n_hyb : n;
+    hipError_t e = hipSuccess;
+    if (nh > 0)
+        e = launch_phi(p->n_phi, p->phi_lines, in, out, items, nh, p->n_theta, p->dev.tw_phi,
+                       p->dev.eneg, pass_args(p, d.phi, d, true), s);
+    if (e == hipSuccess && n > nh)
+        e = launch_phi(p->n_phi, p->phi_lines, in, out, items + nh, n - nh, p->n_theta,
+                       p->dev.tw_phi, p->dev.eneg, pass_args(p, d.phi, d, false), s);
+    return e;
+}
+
 int run_pass(sphfilt_plan p, Pass which, const double *in, double *out, bool all_items,
              const Decisions &d, hipStream_t s)
 {
-    hipError_t e;
-    HybridArgs h = p->hybrid;
-    h.replay = d.replay;
-    if (which == Pass::Theta) {
-        h.dec = d.theta;
-        const int n = all_items ? (int)p->host.theta.size() : p->host.theta_active;
-        e = launch_theta(2 * p->n_theta, p->theta_cols, in, out, p->dev.theta, n, p->n_theta,
-                         p->n_phi, p->dev.tw_theta, p->dev.eneg, h, s);
-    } else {
-        h.dec = d.phi;
-        const int n = all_items ? (int)p->host.phi.size() : p->host.phi_active;
-        e = launch_phi(p->n_phi, p->phi_lines, in, out, p->dev.phi, n, p->n_theta, p->dev.tw_phi,
-                       p->dev.eneg, h, s);
-    }
+    const HostTables &t = p->host;
+    const hipError_t e =
+        which == Pass::Theta
+            ? theta_split(p, in, out, p->dev.theta, all_items ? (int)t.theta.size() : t.theta_active,
+                          t.theta_hyb, d, s)
+            : phi_split(p, in, out, p->dev.phi, all_items ? (int)t.phi.size() : t.phi_active,
+                        t.phi_hyb, d, s);
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
 
@@ -134,14 +170,20 @@ int apply_fused(sphfilt_plan p, bool adjoint, const double *in, double *out, con
 {
     const HostTables &t = p->host;
     if (t.theta_active != t.n_fused) return SPHFILT_EUNSUPPORTED;
-    HybridArgs ht = p->hybrid, hp = p->hybrid;
-    ht.replay = hp.replay = d.replay;
-    ht.dec = d.theta;
-    hp.dec = d.phi;
     const int n_rings = in == out ? t.phi_rest_active : (int)t.phi_rest.size();
-    const hipError_t e = launch_shell_phi(adjoint, p->n_theta, p->n_phi, in, out, p->dev.theta,
-                                          p->dev.fused_c, t.n_fused, p->dev.phi_rest, n_rings,
-                                          p->dev.tw_phi, p->dev.eneg, ht, hp, s);
+    const int nh = t.fused_hyb, lines = p->n_theta / 2;
+    hipError_t e = hipSuccess;
+    // hybrid shells with the hybrid-capable kernel; the other shells and the
+    // rings of the theta-idle shells (never hybrid) with the plain one
+    if (nh > 0)
+        e = launch_shell_phi(adjoint, p->n_theta, p->n_phi, in, out, p->dev.theta, p->dev.fused_c,
+                             nh, p->dev.phi_rest, 0, p->dev.tw_phi, p->dev.eneg,
+                             pass_args(p, d.theta, d, true), pass_args(p, d.phi, d, true), s);
+    if (e == hipSuccess && (t.n_fused > nh || n_rings > 0))
+        e = launch_shell_phi(adjoint, p->n_theta, p->n_phi, in, out, p->dev.theta + nh,
+                             p->dev.fused_c + (size_t)nh * lines, t.n_fused - nh, p->dev.phi_rest,
+                             n_rings, p->dev.tw_phi, p->dev.eneg, pass_args(p, d.theta, d, false),
+                             pass_args(p, d.phi, d, false), s);
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
 
@@ -196,25 +238,18 @@ int apply_overlap(sphfilt_plan p, bool adjoint, double *x, const Decisions &d, h
     const HostTables &t = p->host;
     std::lock_guard<std::mutex> lock(p->side.m);
     if (p->side.state != 1) return SPHFILT_EUNSUPPORTED;
-    HybridArgs ht = p->hybrid, hp = p->hybrid;
-    ht.replay = hp.replay = d.replay;
-    ht.dec = d.theta;
-    hp.dec = d.phi;
     hipStream_t side = p->side.stream;
     hipError_t e = hipEventRecord(p->side.fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, p->side.fork, 0);
-    auto theta = [&]() {
-        return launch_theta(2 * p->n_theta, p->theta_cols, x, x, p->dev.theta, t.theta_active,
-                            p->n_theta, p->n_phi, p->dev.tw_theta, p->dev.eneg, ht, s);
-    };
+    auto theta = [&]() { return theta_split(p, x, x, p->dev.theta, t.theta_active, t.theta_hyb, d, s); };
     auto rings_in = [&]() {
-        return launch_phi(p->n_phi, p->phi_lines, x, x, p->dev.phi_in, (int)t.phi_in.size(),
-                          p->n_theta, p->dev.tw_phi, p->dev.eneg, hp, s);
+        return phi_split(p, x, x, p->dev.phi_in, (int)t.phi_in.size(), t.phi_in_hyb, d, s);
     };
     if (e == hipSuccess) e = adjoint ? rings_in() : theta();
+    // the rings of theta-idle shells: never hybrid
     if (e == hipSuccess)
         e = launch_phi(p->n_phi, p->phi_lines, x, x, p->dev.phi_rest, t.phi_rest_active,
-                       p->n_theta, p->dev.tw_phi, p->dev.eneg, hp, side);
+                       p->n_theta, p->dev.tw_phi, p->dev.eneg, pass_args(p, d.phi, d, false), side);
     if (e == hipSuccess) e = adjoint ? theta() : rings_in();
     if (e == hipSuccess) e = hipEventRecord(p->side.join, side);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p->side.join, 0);
