@@ -309,36 +309,38 @@ template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
 // (|u_{i-1}| + 2|u_i| + |u_{i+1}| + eps) on the two real lines packed in v
 // (periodic along the line).  Returns bit 0 if any cell of the real-part
 // line has sigma >= threshold, bit 1 for the imaginary-part line.  Lanes
-// exchange neighbours through the line's LDS region L and combine their
-// findings in *flag (this line's LDS word).  All lanes call this together;
-// `check` says whether this lane's line needs the detector at all.
+// publish both real lines through the line's LDS region L (2N doubles: the
+// hybrid-capable kernels' line stride) and combine their findings in *flag
+// (this line's LDS word).  All lanes call this together; `check` says whether
+// this lane's line needs the detector at all.
 template <int N1, int N2>
 __device__ __forceinline__ int detect_shocks(const cplx (&v)[N1], int t, double *L, int *flag,
                                              bool check, double eps, double threshold)
 {
     constexpr int N = N1 * N2;
     if (t == 0) *flag = 0;
+    static_for<0, N1>([&](auto nn) {
+        constexpr int n1 = decltype(nn)::value;
+        L[N2 * n1 + t] = v[n1].re;
+        L[N + N2 * n1 + t] = v[n1].im;
+    });
+    __syncthreads();
     int bits = 0;
-    static_for<0, 2>([&](auto part) {
-        constexpr bool im = decltype(part)::value == 1;
-        static_for<0, N1>([&](auto nn) {
-            constexpr int n1 = decltype(nn)::value;
-            L[N2 * n1 + t] = im ? v[n1].im : v[n1].re;
-        });
-        __syncthreads();
-        if (check) {
+    if (check) {
+        static_for<0, 2>([&](auto part) {
+            constexpr bool im = decltype(part)::value == 1;
+            const double *Lp = L + (im ? N : 0);
             static_for<0, N1>([&](auto nn) {
                 constexpr int n1 = decltype(nn)::value;
                 const int n = N2 * n1 + t;
-                const double a = L[(n + N - 1) & (N - 1)];
+                const double a = Lp[(n + N - 1) & (N - 1)];
                 const double b = im ? v[n1].im : v[n1].re;
-                const double c = L[(n + 1) & (N - 1)];
+                const double c = Lp[(n + 1) & (N - 1)];
                 const double sigma = fabs(a - 2.0 * b + c) / (fabs(a) + 2.0 * fabs(b) + fabs(c) + eps);
                 if (sigma >= threshold) bits |= im ? 2 : 1;
             });
-        }
-        __syncthreads();
-    });
+        });
+    }
     if (bits) atomicOr(flag, bits);
     __syncthreads();
     return *flag;
