@@ -105,19 +105,6 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[N1], int t, int kind, doubl
 // as soon as they are formed.  Lines with ka == kb get plain f Z.  All lanes
 // of the workgroup call this together.
 template <int N1, int N2>
-__device__ __forceinline__ double kind_mask(int kind, int qhat, int m, double g_exp,
-                                            double inv_c1, const double *etab)
-{
-    constexpr double inv_n = 1.0 / (N1 * N2);
-    if (kind == 1) {
-        const double u = (double)qhat * inv_c1;
-        return exp(kLog09 * u * u) * inv_n;
-    }
-    if (qhat <= m) return inv_n;
-    return (kind == 0 ? g_exp : 0.0) * etab[qhat - m - 1];
-}
-
-template <int N1, int N2>
 __device__ __forceinline__ void apply_mask_pair(cplx (&v)[N1], int t, int ka, int kb, double c,
                                                 const double *etab, double *P)
 {
@@ -143,8 +130,12 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[N1], int t, int ka, in
             constexpr int k2 = decltype(kk)::value;
             const int q = t + N2 * r + N1 * k2;
             const int qhat = q <= N / 2 ? q : N - q;
-            const double fa = kind_mask<N1, N2>(ka, qhat, m, g_exp, inv_c1, etab);
-            const double fb = ka == kb ? fa : kind_mask<N1, N2>(kb, qhat, m, g_exp, inv_c1, etab);
+            // one Gaussian factor per mode, shared by both kinds
+            const double u = (double)qhat * inv_c1;
+            const double fg = exp(kLog09 * u * u) * inv_n;
+            const double tail = qhat <= m ? inv_n : g_exp * etab[qhat > m ? qhat - m - 1 : 0];
+            const double fa = ka == 1 ? fg : (ka == 0 || qhat <= m ? tail : 0.0);
+            const double fb = kb == 1 ? fg : (kb == 0 || qhat <= m ? tail : 0.0);
             const double alpha = 0.5 * (fa + fb), beta = 0.5 * (fa - fb);
             const int qp = (N - q) & (N - 1);
             v[r * N2 + k2].re = alpha * v[r * N2 + k2].re + beta * P[qp];

@@ -209,3 +209,34 @@ def test_hybrid_batch_equals_plans(torch_gpu):
         assert rel(y.cpu().numpy(), r) <= 1e-14
         ref_o = oracle.forward(p["x"], parity=p["parity"], L=p["L"], kind=p["kind"])
         assert rel(y.cpu().numpy(), ref_o) <= TOL
+
+
+def test_detector_decisions_at_the_threshold(torch_gpu):
+    """Rings with a step from level 1 to 1 + J have largest sigma J / (4 + J + eps):
+    J = 76 puts it on the threshold 0.95, and neighbouring J a few ulps off on
+    either side, where only the rounded quotient decides.  The GPU's decisions
+    equal the oracle's (its quotient is computed exactly as written)."""
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Plan
+    T, P = 16, 32
+    J = [76.0, np.nextafter(76.0, 0.0), np.nextafter(76.0, 100.0), 76.0 * (1 - 1e-15),
+         76.0 * (1 + 1e-15), 76.0 * (1 - 1e-14), 76.0 * (1 + 1e-14), 76.0 * (1 - 3e-13),
+         76.0 * (1 + 3e-13), 75.9, 76.1, 70.0, 80.0, 76.0, 50.0, 120.0]
+    x = np.ones((1, 1, T, P))
+    for j, jj in enumerate(J):
+        x[0, 0, j, P // 2:] = 1.0 + jj
+    eps = 1e-300
+    plan = Plan(1, T, P, 1, parity=[1], L=[0.5], kind=[HYBRID], detector_eps=eps)
+    th, ph = plan.decision_buffers()
+    plan.apply_ex(torch.from_numpy(x).cuda(), adjoint=True, theta_dec=th, phi_dec=ph)
+    torch.cuda.synchronize()
+    try:
+        oracle.set_detector(eps, 0.95)
+        ref = oracle.decisions(x, parity=np.array([1]), kind=np.array([HYBRID]))[1]
+    finally:
+        oracle.set_detector()
+    got = ph.cpu().numpy()
+    print(f"[gpu] threshold decisions gpu {got.ravel().tolist()} oracle {ref.ravel().tolist()}", flush=True)
+    assert np.array_equal(got, ref)
+    assert 0 < int(ref.sum()) < T          # both outcomes occur
+    plan.close()
