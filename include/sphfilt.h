@@ -321,7 +321,9 @@ int sphfilt_batch_tune(sphfilt_batch batch, const char *tune_cache_path);
  *   workgroups_per_cu  -1: one workgroup per work item (each takes one item
  *                      and exits).  k > 0: a persistent grid of k workgroups
  *                      per compute unit looping over items; 0 = the most
- *                      that fit.
+ *                      that fit.  k above the most that fit (the occupancy
+ *                      of the persistent kernel: 1 on batches with hybrid
+ *                      fields) is SPHFILT_EINVAL.
  * get_schedule also returns the tuned time of one call in microseconds
  * (negative when not tuned).  Results do not depend on the schedule.
  */

@@ -177,6 +177,14 @@ def test_batch_schedule_values(torch_gpu):
         batch.set_schedule(3, -1)
     with pytest.raises(SphfiltError):
         batch.set_schedule(0, -2)
+    # 0 selects the most persistent workgroups per compute unit that fit; one
+    # more than that is rejected
+    batch.set_schedule(0, 0)
+    most = batch.get_schedule()["workgroups_per_cu"]
+    assert most >= 1
+    batch.set_schedule(1, most)
+    with pytest.raises(SphfiltError):
+        batch.set_schedule(1, most + 1)
     batch.close()
 
 
