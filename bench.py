@@ -337,7 +337,7 @@ def bench_short_lines(torch, steps, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
                                    "(the filter never couples shells, so a multi-GPU run is a "
                                    "(field, r) split with no communication)"}))
         return 2

@@ -34,7 +34,7 @@
  * validated on the host before any device call.  Device entry points only
  * enqueue work on the given HIP stream and return; the caller synchronises.
  *
- * Supported sizes in this build: 2*n_theta and n_phi each in
+ * Supported sizes: 2*n_theta and n_phi each in
  * {32, 64, 128, 256}; other sizes return SPHFILT_EUNSUPPORTED.
  */
 #ifndef SPHFILT_H
@@ -130,7 +130,7 @@ typedef struct {
  * concurrently on several streams.
  * Returns SPHFILT_EINVAL for n_* <= 0, odd n_phi, NULL pointers, parity not
  * +-1, non-finite or non-positive rho / L, unknown kind, bad floor;
- * SPHFILT_EUNSUPPORTED for sizes outside this build; SPHFILT_ENOMEM /
+ * SPHFILT_EUNSUPPORTED for unsupported sizes; SPHFILT_ENOMEM /
  * SPHFILT_EDEVICE when allocation or upload fails.
  */
 int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int n_fields,

@@ -460,7 +460,7 @@ const char *sphfilt_status_string(int status)
     case SPHFILT_EINVAL: return "invalid argument";
     case SPHFILT_ENOMEM: return "out of memory";
     case SPHFILT_EDEVICE: return "HIP device or launch error";
-    case SPHFILT_EUNSUPPORTED: return "size not supported by this build";
+    case SPHFILT_EUNSUPPORTED: return "size not supported by the library";
     default: return "unknown status";
     }
 }
