@@ -40,6 +40,24 @@ __device__ __forceinline__ double ld_stream(const double *p)
 #endif
 }
 
+// Loads whose instruction reads only a piece of each 128-byte line it
+// touches go through the cache instead: rings of N <= 64 points (4 or 8 lanes
+// per ring: 32- or 64-byte pieces) and theta rows at N = 32 (sub-tiles of 8
+// meridians).  Streamed, the other pieces of a line were fetched again (1.32x
+// the algorithmic bytes for rings of 32, 1.09x for rings of 64).
+template <bool CACHED>
+__device__ __forceinline__ double ld_piece(const double *p)
+{
+    if constexpr (CACHED)
+        return *p;
+    else
+        return ld_stream(p);
+}
+template <int N>
+constexpr bool ring_loads_cached() { return N <= 64; }
+template <int N>
+constexpr bool theta_loads_cached() { return N <= 32; }
+
 template <bool NT = true>
 __device__ __forceinline__ void st_stream(double *p, double v)
 {
@@ -417,11 +435,13 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
         if (!valid) {
             v[n1] = cplx{0.0, 0.0};
         } else if constexpr (n1 < N1 / 2) {
+            constexpr bool cached = theta_loads_cached<N>();
             const double *row = in + base + (size_t)(N2 * n1) * n_phi;
-            v[n1] = cplx{ld_stream(row + off_n + kr), ld_stream(row + off_n + ki)};
+            v[n1] = cplx{ld_piece<cached>(row + off_n + kr), ld_piece<cached>(row + off_n + ki)};
         } else {
+            constexpr bool cached = theta_loads_cached<N>();
             const double *row = in + base + (size_t)(N - N2 * (n1 + 1)) * n_phi;
-            v[n1] = cplx{s * ld_stream(row + off_s + kr), s * ld_stream(row + off_s + ki)};
+            v[n1] = cplx{s * ld_piece<cached>(row + off_s + kr), s * ld_piece<cached>(row + off_s + ki)};
         }
     });
     // Identity lines sharing a workgroup with filtered ones run through the
@@ -489,7 +509,8 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
     cplx v[N1];
     static_for<0, N1>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
-        v[n1] = valid ? cplx{ld_stream(in + a + N2 * n1 + t), ld_stream(in + b + N2 * n1 + t)}
+        constexpr bool cached = ring_loads_cached<N>();
+        v[n1] = valid ? cplx{ld_piece<cached>(in + a + N2 * n1 + t), ld_piece<cached>(in + b + N2 * n1 + t)}
                       : cplx{0.0, 0.0};
     });
     if (any_active) {
