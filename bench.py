@@ -86,6 +86,8 @@ def parse():
                          "as JSON (for profiling the fused shell kernel)")
     ap.add_argument("--short-lines-only", action="store_true",
                     help="time only the dense short-line grids (n_phi = 32, 64, 128)")
+    ap.add_argument("--radix3-only", action="store_true",
+                    help="time only the 96 x 192 grid (lines with a radix-3 stage)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -296,6 +298,40 @@ def bench_hybrid(torch, w, bufs, steps, stream):
             "algorithmic_bytes": st["bytes_forward_inplace"]}
 
 
+def bench_radix3(torch, steps, stream):
+    """Lines with a radix-3 stage: 24 fields x 128 shells x 96 x 192 (the
+    angular grid of the paper's FFT(96) black-hole run), rho = i + 1/2, at the
+    paper's cutoff cal-L = 2 (that run's value) and dense (every line
+    filtered, rho = 1, cal-L = 0.2): each pass and the forward filter in place."""
+    import numpy as np
+    from paper_2305_01537_amd.filter import Plan
+    F, R, T, P = 24, 128, 96, 192
+    g = torch.Generator(device="cuda").manual_seed(192)
+    x0 = torch.randn((F, R, T, P), dtype=torch.float64, device="cuda", generator=g)
+    bufs = [x0, x0.clone()]
+    parity = np.where(np.arange(F) % 3 == 2, -1, 1)
+    out = {"shape": [F, R, T, P]}
+    for name, L, rho in (("paper_cutoff", 2.0, None), ("dense", 0.2, np.ones(R))):
+        plan = Plan(R, T, P, F, parity=parity, L=L, rho=rho)
+        st = plan.stats()
+        ms_t = time_loop(torch, lambda b: plan.apply_theta(b, out=b), bufs, steps, 5, stream)
+        ms_p = time_loop(torch, lambda b: plan.apply_phi(b, out=b), bufs, steps, 5, stream)
+        ms_f = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 5, stream)
+        tb = 16 * st["theta_shells_active"] * T * P
+        pb = 16 * st["phi_rings_active"] * P
+        out[name] = {"cal_L": L, "forward_ms": ms_f,
+                     "points_per_s": st["n_points"] / (ms_f * 1e-3),
+                     "step_GBps": st["bytes_forward_inplace"] / (ms_f * 1e-3) / 1e9,
+                     "theta_GBps": tb / (ms_t * 1e-3) / 1e9 if tb else None,
+                     "phi_GBps": pb / (ms_p * 1e-3) / 1e9 if pb else None,
+                     "active_theta_shells": st["theta_shells_active"],
+                     "active_phi_rings": st["phi_rings_active"]}
+        plan.close()
+    del bufs, x0
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_short_lines(torch, steps, stream):
     """Dense cutoff (every line filtered) on grids with short lines,
     n_phi = 2 n_theta = 32, 64, 128, 24 fields and about 800 MB per buffer
@@ -358,6 +394,9 @@ def main():
         return 0
     if args.short_lines_only:
         print(json.dumps({"short_lines": bench_short_lines(torch, args.steps, stream)}), flush=True)
+        return 0
+    if args.radix3_only:
+        print(json.dumps({"radix3": bench_radix3(torch, args.steps, stream)}), flush=True)
         return 0
 
     log("generating the share workload (24 x 256 x 128 x 256, FP64)")
@@ -465,6 +504,9 @@ def main():
         log("timing dense short-line grids")
         extra["short_lines"] = bench_short_lines(torch, max(10, args.steps // 2), stream)
         log(f"short lines: {extra['short_lines']}")
+        log("timing radix-3 lines (96 x 192)")
+        extra["radix3"] = bench_radix3(torch, max(10, args.steps // 2), stream)
+        log(f"radix-3 lines: {extra['radix3']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -232,6 +232,8 @@ void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
     }
 }
 
+bool batch_line(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+
 // A patch whose theta-filtered shells are all fused (n_phi = 2 n_theta <= 128,
 // see build_items) runs entirely in the first pass: groups of whole shells
 // (both passes, add_fused_shells), and the ring pairs of its theta-idle shells
@@ -606,6 +608,9 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
         const sphfilt_patch_desc &d = desc[p];
         const int rc = validate(d.n_r, d.n_theta, d.n_phi, d.n_fields, d.parity, &d.cut);
         if (rc) return rc;
+        // the batch kernel carries the power-of-two line lengths only (the
+        // radix-3 ones would raise its register count for every item)
+        if (!batch_line(2 * d.n_theta) || !batch_line(d.n_phi)) return SPHFILT_EUNSUPPORTED;
         shells += (long long)d.n_fields * d.n_r;
     }
     if (shells > 0x7fffffffLL) return SPHFILT_EUNSUPPORTED;

@@ -116,14 +116,101 @@ __device__ __forceinline__ cplx twiddle_const(cplx a)
     }
 }
 
+// cos(a pi / 12) for a in [0, 6] ((sqrt6 +- sqrt2)/4, sqrt3/2, sqrt2/2, 1/2),
+// to 25 digits; and for any integer a by the quadrant symmetries.
+constexpr double cos_pi12_q(int a)
+{
+    return a == 0   ? 1.0
+           : a == 1 ? 0.9659258262890682867497432
+           : a == 2 ? 0.8660254037844386467637232
+           : a == 3 ? 0.7071067811865475244008444
+           : a == 4 ? 0.5
+           : a == 5 ? 0.2588190451025207623488988
+                    : 0.0;
+}
+constexpr double cos_pi12(int a)
+{
+    a = ((a % 24) + 24) % 24;
+    return a <= 6 ? cos_pi12_q(a) : a <= 12 ? -cos_pi12_q(12 - a) : a <= 18 ? -cos_pi12_q(a - 12) : cos_pi12_q(24 - a);
+}
+constexpr double sin_pi12(int a) { return cos_pi12(6 - a); }
+
+// a * exp(-i A pi / 12) (forward) or exp(+i A pi / 12) (INV): the twiddles of
+// the transforms whose size divides 24.
+template <int A, bool INV>
+__device__ __forceinline__ cplx twiddle_pi12(cplx a)
+{
+    constexpr int a0 = ((A % 24) + 24) % 24;
+    constexpr int e = INV ? a0 : (24 - a0) % 24;         // exp(i e pi / 12)
+    if constexpr (e == 0) {
+        return a;
+    } else if constexpr (e == 12) {
+        return {-a.re, -a.im};
+    } else if constexpr (e == 6) {
+        return {-a.im, a.re};
+    } else if constexpr (e == 18) {
+        return {a.im, -a.re};
+    } else {
+        constexpr double c = cos_pi12(e), s = sin_pi12(e);
+        return {a.re * c - a.im * s, a.re * s + a.im * c};
+    }
+}
+
+// 3-point DFT of (x0, x1, x2) in place: with s = x1 + x2 and d = x1 - x2,
+// X0 = x0 + s and X1, X2 = x0 - s/2 -+ i (sqrt3/2) d (forward; INV swaps the
+// signs of the i (sqrt3/2) d term).
+template <bool INV>
+__device__ __forceinline__ void dft3(cplx &x0, cplx &x1, cplx &x2)
+{
+    constexpr double h = 0.8660254037844386467637232;   // sqrt(3)/2
+    const cplx s = cadd(x1, x2), d = csub(x1, x2);
+    const cplx m = {x0.re - 0.5 * s.re, x0.im - 0.5 * s.im};
+    const cplx j = INV ? cplx{-h * d.im, h * d.re} : cplx{h * d.im, -h * d.re};   // -+i h d
+    x0 = cadd(x0, s);
+    x1 = cadd(m, j);
+    x2 = csub(m, j);
+}
+
 // In-register DFT of size R on v[OFF + STRIDE*i], i in [0, R): natural order
 // in, natural order out.  Forward: exp(-2 pi i n k / R); INV: exp(+...),
-// unnormalised.
+// unnormalised.  R is a power of two up to 64, or 3 times a power of two
+// dividing 24 (R = 3, 6, 12, 24): then, with R = 3 B, n = b + B a and
+// k = ka + 3 kb,
+//   X[ka + 3 kb] = sum_b W_B^{b kb} W_R^{b ka} sum_a x[b + B a] W_3^{a ka},
+// i.e. 3-point DFTs over a, twiddles W_R^{b ka}, B-point DFTs over b, and a
+// register renaming to natural order.
 template <int R, bool INV, int OFF = 0, int STRIDE = 1, int NV>
 __device__ __forceinline__ void dft_reg(cplx (&v)[NV])
 {
-    static_assert((R & (R - 1)) == 0 && R >= 1 && R <= 64, "radix must be a power of two <= 64");
-    if constexpr (R > 1) {
+    if constexpr (R % 3 == 0) {
+        static_assert(24 % R == 0, "a radix-3 transform size must divide 24");
+        constexpr int B = R / 3;
+        static_for<0, B>([&](auto bb) {
+            constexpr int b = decltype(bb)::value;
+            constexpr int p0 = OFF + STRIDE * b, p1 = p0 + STRIDE * B, p2 = p1 + STRIDE * B;
+            dft3<INV>(v[p0], v[p1], v[p2]);
+            // W_R^{b ka} = exp(-+ i (24 / R) b ka pi / 12)
+            v[p1] = twiddle_pi12<(24 / R) * b, INV>(v[p1]);
+            v[p2] = twiddle_pi12<(24 / R) * 2 * b, INV>(v[p2]);
+        });
+        static_for<0, 3>([&](auto aa) {
+            dft_reg<B, INV, OFF + STRIDE * B * decltype(aa)::value, STRIDE>(v);
+        });
+        // X[ka + 3 kb] sits at position ka B + kb
+        cplx tmp[R];
+        static_for<0, R>([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            tmp[k] = v[OFF + STRIDE * ((k % 3) * B + k / 3)];
+        });
+        static_for<0, R>([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            v[OFF + STRIDE * k] = tmp[k];
+        });
+        return;
+    }
+    static_assert(R % 3 == 0 || ((R & (R - 1)) == 0 && R >= 1 && R <= 64),
+                  "radix must be a power of two <= 64");
+    if constexpr (R > 1 && R % 3 != 0) {
         // decimation in frequency: spans R/2, R/4, ..., 1; output bit-reversed
         static_for<0, ilog2(R)>([&](auto st) {
             constexpr int span = R >> (decltype(st)::value + 1);

@@ -20,7 +20,10 @@ bool fault(const char *what)
     return e && std::strcmp(e, what) == 0;
 }
 
-bool supported_line(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+bool supported_line(int n)
+{
+    return n == 32 || n == 48 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256;
+}
 
 // cos and sin of 2 pi j / N, reducing the angle to the first octant with
 // integer arithmetic so the table is accurate to the last bit or so.

@@ -13,10 +13,20 @@
 
 namespace sphfilt {
 
+// Waves per SIMD the hybrid-capable instances aim for: two where two
+// workgroups' line scratch (a whole spectrum per line) fits in LDS, else one
+// (lines of 96 and 192 at 256 lanes).
+template <int N, int LINES, bool HYB>
+constexpr int pass_waves()
+{
+    constexpr int bytes = 8 * LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
+    return (HYB || N == 192) && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
+}
+
 // theta-pass: workgroup b handles shell group g = b / tiles (S = C / cp shells
 // of the item list) and meridian tile b % tiles.
 template <int N, int C, bool HYB>
-__global__ __launch_bounds__(C * Split<N>::N2) __attribute__((amdgpu_waves_per_eu(HYB ? 2 : 1))) void theta_kernel(
+__global__ __launch_bounds__(C * Split<N>::N2) __attribute__((amdgpu_waves_per_eu(pass_waves<N, C, HYB>()))) void theta_kernel(
     const double *in, double *out, const ThetaItem *__restrict__ items, int n_items, int cp_log2,
     int tiles, int n_theta, int n_phi, const Twiddle *__restrict__ tw,
     const double *__restrict__ eneg, HybridArgs h)
@@ -35,7 +45,7 @@ __global__ __launch_bounds__(C * Split<N>::N2) __attribute__((amdgpu_waves_per_e
 
 // phi-pass: workgroup b handles ring pairs [b * LINES, b * LINES + LINES).
 template <int N, int LINES, bool HYB>
-__global__ __launch_bounds__(LINES * Split<N>::N2) __attribute__((amdgpu_waves_per_eu(HYB ? 2 : 1))) void phi_kernel(
+__global__ __launch_bounds__(LINES * Split<N>::N2) __attribute__((amdgpu_waves_per_eu(pass_waves<N, LINES, HYB>()))) void phi_kernel(
     const double *in, double *out, const PhiItem *__restrict__ items, int n_items, int n_theta,
     const Twiddle *__restrict__ tw, const double *__restrict__ eneg, HybridArgs h)
 {
@@ -85,8 +95,11 @@ int lanes_per_line(int n_line)
 {
     switch (n_line) {
     case 32: return Split<32>::N2;
+    case 48: return Split<48>::N2;
     case 64: return Split<64>::N2;
+    case 96: return Split<96>::N2;
     case 128: return Split<128>::N2;
+    case 192: return Split<192>::N2;
     case 256: return Split<256>::N2;
     default: return 0;
     }
@@ -106,9 +119,13 @@ int theta_lines_per_group(int n_line)
 
 int default_theta_cols(int n_line, int n_phi)
 {
+    // the widest power-of-two tile within the workgroup's lines and n_phi/4
+    // whose pairs of sub-tiles divide the n_phi/2 meridian pairs
     const int c = theta_lines_per_group(n_line);
-    const int cap = n_phi / 4;
-    return c < cap ? c : cap;
+    int cols = 4;
+    while (cols * 2 <= c && cols * 2 <= n_phi / 4) cols *= 2;
+    while (cols > 4 && (n_phi / 2) % (2 * cols) != 0) cols /= 2;
+    return cols;
 }
 
 int default_phi_lines(int n_line)
@@ -119,7 +136,7 @@ int default_phi_lines(int n_line)
 bool theta_shape_ok(int n_line, int cols, int n_phi)
 {
     const int c = theta_lines_per_group(n_line);
-    return c > 0 && (cols == 8 || cols == 16 || cols == 32 || cols == 64) && cols <= c &&
+    return c > 0 && (cols == 4 || cols == 8 || cols == 16 || cols == 32 || cols == 64) && cols <= c &&
            (n_phi / 2) % (2 * cols) == 0;
 }
 
@@ -164,8 +181,11 @@ hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
     if (!theta_shape_ok(n_line, cols, n_phi) || n_line != 2 * n_theta) return hipErrorInvalidValue;
     switch (n_line) {
     case 32: return theta_go<32>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
+    case 48: return theta_go<48>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 64: return theta_go<64>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
+    case 96: return theta_go<96>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 128: return theta_go<128>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
+    case 192: return theta_go<192>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 256: return theta_go<256>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     default: return hipErrorInvalidValue;
     }
@@ -213,8 +233,11 @@ hipError_t launch_phi(int n_line, int lines, const double *in, double *out, cons
     if (!phi_shape_ok(n_line, lines)) return hipErrorInvalidValue;
     switch (n_line) {
     case 32: return phi_lines<32>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
+    case 48: return phi_lines<48>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 64: return phi_lines<64>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
+    case 96: return phi_lines<96>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 128: return phi_lines<128>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
+    case 192: return phi_lines<192>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 256: return phi_lines<256>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     default: return hipErrorInvalidValue;
     }

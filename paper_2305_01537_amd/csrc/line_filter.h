@@ -155,7 +155,7 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[N1], int t, int ka, in
             const double fa = ka == 1 ? fg : (ka == 0 || qhat <= m ? tail : 0.0);
             const double fb = kb == 1 ? fg : (kb == 0 || qhat <= m ? tail : 0.0);
             const double alpha = 0.5 * (fa + fb), beta = 0.5 * (fa - fb);
-            const int qp = (N - q) & (N - 1);
+            const int qp = (N - q) % N;
             v[r * N2 + k2].re = alpha * v[r * N2 + k2].re + beta * P[qp];
             v[r * N2 + k2].im = alpha * v[r * N2 + k2].im - beta * P[N + qp];
         });
@@ -307,10 +307,16 @@ __device__ __forceinline__ void stage_exp_table(double *etab, const double *__re
     for (int i = lane; i <= N / 2; i += (int)blockDim.x) etab[i] = eneg[i];
 }
 
+// N = N1 * N2: N2 lanes per line, N1 values per lane; N2 divides N1 (the
+// transpose gives each lane N1 / N2 whole second-stage transforms).  The
+// lengths 48, 96 and 192 take a radix-3 stage in the N1-point transform.
 template <int N> struct Split;
 template <> struct Split<32>  { static constexpr int N1 = 8,  N2 = 4; };
+template <> struct Split<48>  { static constexpr int N1 = 12, N2 = 4; };
 template <> struct Split<64>  { static constexpr int N1 = 8,  N2 = 8; };
+template <> struct Split<96>  { static constexpr int N1 = 24, N2 = 4; };
 template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
+template <> struct Split<192> { static constexpr int N1 = 24, N2 = 8; };
 template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
 
 
@@ -342,9 +348,9 @@ __device__ __forceinline__ int detect_shocks(const cplx (&v)[N1], int t, double 
             static_for<0, N1>([&](auto nn) {
                 constexpr int n1 = decltype(nn)::value;
                 const int n = N2 * n1 + t;
-                const double a = Lp[(n + N - 1) & (N - 1)];
+                const double a = Lp[(n + N - 1) % N];
                 const double b = im ? v[n1].im : v[n1].re;
-                const double c = Lp[(n + 1) & (N - 1)];
+                const double c = Lp[(n + 1) % N];
                 const double sigma = fabs(a - 2.0 * b + c) / (fabs(a) + 2.0 * fabs(b) + fabs(c) + eps);
                 if (sigma >= threshold) bits |= im ? 2 : 1;
             });

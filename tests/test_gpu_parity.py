@@ -80,7 +80,10 @@ def test_grmhd_slice(torch_gpu, L):
 
 
 @pytest.mark.parametrize("n_theta,n_phi", [(16, 32), (16, 64), (32, 64), (32, 32), (64, 128),
-                                           (64, 256), (128, 256), (128, 64), (16, 256), (128, 32)])
+                                           (64, 256), (128, 256), (128, 64), (16, 256), (128, 32),
+                                           # lines with a radix-3 stage (48, 96, 192)
+                                           (24, 48), (48, 96), (96, 192), (96, 128), (64, 192),
+                                           (24, 256), (128, 96), (16, 48), (96, 32), (48, 192)])
 def test_every_supported_size(torch_gpu, n_theta, n_phi):
     rng = np.random.default_rng(n_theta * 1000 + n_phi)
     shape = (3, 5, n_theta, n_phi)
@@ -195,3 +198,41 @@ def test_share_full_size_sampled_shells(torch_gpu):
             assert rel(fwd[f:f + 1, i:i + 1], oracle.forward(sub, **kw)) <= TOL, (L, f, i)
             assert rel(adj[f:f + 1, i:i + 1], oracle.adjoint(sub, **kw)) <= TOL, (L, f, i)
         plan.close()
+
+
+@pytest.mark.parametrize("n_theta,n_phi", [(96, 192), (48, 96), (24, 48)])
+def test_radix3_grid_schedules_and_hybrid(torch_gpu, n_theta, n_phi):
+    """Lines with a radix-3 stage: every theta tile that divides the meridian
+    pairs and every phi launch shape give results within rounding of each
+    other (the phi shape bitwise) and of the oracle; hybrid fields too."""
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Plan, SphfiltError
+    rng = np.random.default_rng(n_phi)
+    shape = (3, 4, n_theta, n_phi)
+    x = rng.standard_normal(shape) + 2.0
+    x[2, 1, :, : n_phi // 3] = 0.0                           # a jump for the hybrid field
+    parity = np.array([1, -1, 1], dtype=np.int32)
+    kind = np.array([0, 2, 3], dtype=np.int32)
+    L = np.array([0.4, 1.3, 0.9])
+    print(f"[gpu] radix-3 schedules {shape}", flush=True)
+    plan = Plan(4, n_theta, n_phi, 3, parity=parity, L=L, kind=kind)
+    ref = oracle.forward(x, parity=parity, L=L, kind=kind)
+    outs = []
+    for cols in (4, 8, 16, 32, 64):
+        try:
+            plan.set_schedule(theta_cols=cols)
+        except SphfiltError:
+            continue
+        for lines in (4, 16, 64):
+            try:
+                plan.set_schedule(phi_lines=lines)
+            except SphfiltError:
+                continue
+            y = gpu_call(torch, plan, "forward", x, inplace=False)
+            assert rel(y, ref) <= TOL, (cols, lines, rel(y, ref))
+            outs.append((cols, lines, y))
+    assert len(outs) >= 3
+    for cols, lines, y in outs:
+        same_cols = [z for c, l, z in outs if c == cols]
+        assert all(bitwise(y, z) for z in same_cols), (cols, lines)
+    plan.close()

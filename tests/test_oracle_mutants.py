@@ -71,7 +71,7 @@ def _pin_cases():
     P = pins
     return [
         lambda m: [P.test_p1_constant_even_parity(m, k) for k in (0, 1, 2)],
-        lambda m: [P.test_p3_separable_eigenmodes(m, k, s) for k in (0, 1, 2) for s in (1, -1)],
+        lambda m: [P.test_p3_separable_eigenmodes(m, k, s, 16, 32) for k in (0, 1, 2) for s in (1, -1)],
         lambda m: P.test_p3_order_matters(m),
         lambda m: [P.test_p5_phi_rotation_equivariance(m, s) for s in (1, -1)],
         lambda m: [P.test_p5_equatorial_reflection(m, s) for s in (1, -1)],
@@ -80,6 +80,7 @@ def _pin_cases():
         lambda m: P.test_p8_paper_constants(m),
         lambda m: P.test_p8_cutoff_depends_on_r_and_latitude(m),
         lambda m: [P.test_p10_library_fft_matches(m, k) for k in (0, 1, 2)],
+        lambda m: P.test_p10_library_fft_matches_radix3_lengths(m, 24, 48),
         lambda m: P.test_hybrid_smooth_fields_take_the_exponential_filter(m),
         lambda m: P.test_hybrid_ring_with_a_jump_takes_the_gaussian(m),
         lambda m: P.test_hybrid_theta_decision_uses_the_extended_line(m),

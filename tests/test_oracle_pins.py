@@ -235,8 +235,9 @@ def test_p2_high_m_is_damped_near_poles(oracle_mod):
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", [EXP, GAUSS, SHARP])
 @pytest.mark.parametrize("s", [1, -1])
-def test_p3_separable_eigenmodes(oracle_mod, kind, s):
-    R, T, P = 3, 16, 32
+@pytest.mark.parametrize("T,P", [(16, 32), (24, 48), (48, 96)])
+def test_p3_separable_eigenmodes(oracle_mod, kind, s, T, P):
+    R = 3
     rho = np.array([0.5, 1.5, 4.5])
     L = 0.9
     theta, phi = synth.theta_grid(T), synth.phi_grid(P)
@@ -427,6 +428,22 @@ def test_p10_library_fft_matches(oracle_mod, kind):
         assert imag <= 1e-14 * np.abs(ref).max()
         refa = fft_theta_pass(fft_phi_pass(w.x, w.parity, w.rho, Lv, kinds), w.parity, w.rho, Lv, kinds)
         assert rel_err(oracle_mod.adjoint(w.x, parity=w.parity, rho=w.rho, L=L, kind=kind), refa) <= 1e-13
+
+
+@pytest.mark.parametrize("T,P", [(96, 192), (48, 96), (24, 48)])
+def test_p10_library_fft_matches_radix3_lengths(oracle_mod, T, P):
+    # lines of 3 * 2^k points: numpy's FFT against the oracle's direct DFTs
+    rng = np.random.default_rng(T)
+    x = rng.standard_normal((2, 3, T, P))
+    parity = np.array([1, -1])
+    rho = np.array([0.5, 3.5, 9.5])
+    Lv = np.array([2.0, 0.7])
+    kinds = np.array([EXP, GAUSS])
+    ref = fft_phi_pass(fft_theta_pass(x, parity, rho, Lv, kinds), parity, rho, Lv, kinds)
+    got = oracle_mod.forward(x, parity=parity, rho=rho, L=Lv, kind=kinds)
+    assert rel_err(got, ref) <= 1e-13
+    refa = fft_theta_pass(fft_phi_pass(x, parity, rho, Lv, kinds), parity, rho, Lv, kinds)
+    assert rel_err(oracle_mod.adjoint(x, parity=parity, rho=rho, L=Lv, kind=kinds), refa) <= 1e-13
 
 
 def test_p10_library_fft_matches_grmhd_slice(oracle_mod):
