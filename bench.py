@@ -37,12 +37,25 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2305_01537_amd", "csrc", f)
                   for f in ("kernels.hip", "line_filter.h", "fft_core.h", "sphfilt_internal.h")]
 
 
-def kernel_source_hash():
+def code_tokens(text):
+    """C++ source with comments removed and whitespace collapsed: the code
+    the counters were taken on (comment edits do not change it)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(read=None):
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(f, encoding="utf-8") as fh:
+                text = fh.read()
+        else:
+            text = read(f)
+        h.update(code_tokens(text).encode())
     return h.hexdigest()[:16]
 
 

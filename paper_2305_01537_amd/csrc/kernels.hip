@@ -13,9 +13,13 @@
 
 namespace sphfilt {
 
-// Waves per SIMD the hybrid-capable instances aim for: two where two
+// Waves per SIMD a pass kernel asks the compiler for (it caps the registers
+// per lane at 512 / waves).  The hybrid-capable instances: two, where two
 // workgroups' line scratch (a whole spectrum per line) fits in LDS, else one
-// (lines of 96 and 192 at 256 lanes).
+// (lines of 96 and 192 at 256 lanes).  The plain instances at N = 192: two
+// as well, for a 4-12 register spill; they would otherwise take a little over
+// 256 registers and run one wave.  The other plain instances: no target
+// (they fit two or more waves by themselves).
 template <int N, int LINES, bool HYB>
 constexpr int pass_waves()
 {
