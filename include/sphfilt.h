@@ -35,9 +35,8 @@
  * enqueue work on the given HIP stream and return; the caller synchronises.
  *
  * Supported sizes: 2*n_theta and n_phi each in
- * {32, 48, 64, 96, 128, 192, 256} for plans (48, 96 and 192 are transformed
- * with a radix-3 stage); batches take {32, 64, 128, 256}.  Other sizes return
- * SPHFILT_EUNSUPPORTED.
+ * {32, 48, 64, 96, 128, 192, 256} (48, 96 and 192 are transformed with a
+ * radix-3 stage); other sizes return SPHFILT_EUNSUPPORTED.
  */
 #ifndef SPHFILT_H
 #define SPHFILT_H
@@ -273,10 +272,10 @@ typedef struct {
 /*
  * Create a batch of n_patches patches on the current HIP device.
  *   desc             [n_patches] patch descriptions; validated like
- *                    sphfilt_plan_create (same error codes), and lines of 48,
- *                    96 or 192 points are SPHFILT_EUNSUPPORTED here (the
- *                    batch kernel carries the power-of-two lengths only).
- *                    Read during the call only.
+ *                    sphfilt_plan_create (same error codes).  A batch with a
+ *                    line of 48, 96 or 192 points runs a kernel instance that
+ *                    carries those lengths too (one wave per SIMD).  Read
+ *                    during the call only.
  *   tune_cache_path  NULL: use the default schedule (no tuning).  Otherwise
  *                    a JSON file: if it holds a schedule for this set of
  *                    patches on this GPU architecture, that schedule is used;

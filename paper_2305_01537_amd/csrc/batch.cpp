@@ -88,6 +88,7 @@ struct sphfilt_batch_s {
     std::vector<GraphEntry> graphs;
     int split = 0, wpc = -1;           // schedule: see effective_wpc
     int hybrid = 0;                    // some patch has a hybrid field
+    int variant = 0;                   // kernel instance: kBatchHybrid | kBatchRadix3
     double tuned_us = -1.0;
     uint64_t clock = 0;
     hipStream_t capture_stream = nullptr;
@@ -232,7 +233,8 @@ void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
     }
 }
 
-bool batch_line(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+// Lines of 48, 96 or 192 points take the batch kernel's radix-3 instance.
+bool radix3_line(int n) { return n == 48 || n == 96 || n == 192; }
 
 // A patch whose theta-filtered shells are all fused (n_phi = 2 n_theta <= 128,
 // see build_items) runs entirely in the first pass: groups of whole shells
@@ -345,30 +347,30 @@ int record(sphfilt_batch b, const ModeWork &m, const GraphEntry &g, hipStream_t 
         if (e == hipSuccess)
             e = launch_batch(grid, m.d_work + m.n_first, m.n_indep, b->d_patches, g.d_ins, g.d_outs,
                              b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
-                             b->d_tickets + 2, b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid,
+                             b->d_tickets + 2, b->d_error, b->d_eneg, 0, kSpinLimit, b->variant,
                              b->side_stream);
         if (e == hipSuccess)
             e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th,
                              b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets,
-                             b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid, s);
+                             b->d_error, b->d_eneg, 0, kSpinLimit, b->variant, s);
         if (e == hipSuccess)
             e = launch_batch(grid, m.d_work + dep0, m.n_work - dep0, b->d_patches, g.d_ins, g.d_outs,
                              b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
-                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid, s);
+                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->variant, s);
         if (e == hipSuccess) e = hipEventRecord(b->join, b->side_stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join, 0);
     } else if (g.split) {
         e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
                          b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg,
-                         0, kSpinLimit, b->hybrid, s);
+                         0, kSpinLimit, b->variant, s);
         if (e == hipSuccess)
             e = launch_batch(grid, m.d_work + m.n_first, m.n_work - m.n_first, b->d_patches, g.d_ins,
                              g.d_outs, b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
-                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->hybrid, s);
+                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->variant, s);
     } else {
         e = launch_batch(grid, m.d_work, m.n_work, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
                          b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg, 1,
-                         kSpinLimit, b->hybrid, s);
+                         kSpinLimit, b->variant, s);
     }
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
@@ -608,9 +610,6 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
         const sphfilt_patch_desc &d = desc[p];
         const int rc = validate(d.n_r, d.n_theta, d.n_phi, d.n_fields, d.parity, &d.cut);
         if (rc) return rc;
-        // the batch kernel carries the power-of-two line lengths only (the
-        // radix-3 ones would raise its register count for every item)
-        if (!batch_line(2 * d.n_theta) || !batch_line(d.n_phi)) return SPHFILT_EUNSUPPORTED;
         shells += (long long)d.n_fields * d.n_r;
     }
     if (shells > 0x7fffffffLL) return SPHFILT_EUNSUPPORTED;
@@ -658,12 +657,16 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
             b->arch = prop.gcnArchName;
             const size_t colon = b->arch.find(':');
             if (colon != std::string::npos) b->arch.resize(colon);
-            for (int p = 0; p < n_patches; ++p)
+            bool r3 = false;
+            for (int p = 0; p < n_patches; ++p) {
                 b->hybrid |= hybrid_args(&desc[p].cut, desc[p].n_fields).present;
-            b->max_wpc = batch_blocks_per_cu(b->hybrid);
+                r3 = r3 || radix3_line(2 * desc[p].n_theta) || radix3_line(desc[p].n_phi);
+            }
+            b->variant = (b->hybrid ? kBatchHybrid : 0) | (r3 ? kBatchRadix3 : 0);
+            b->max_wpc = batch_blocks_per_cu(b->variant);
             b->signature = signature(b->arch, n_patches, desc);
         }
-        for (int N : {32, 64, 128, 256}) {
+        for (int N : {32, 48, 64, 96, 128, 192, 256}) {
             if (rc) break;
             bool used = false;
             for (const PatchHost &h : b->patches) used |= (2 * h.n_theta == N) || (h.n_phi == N);

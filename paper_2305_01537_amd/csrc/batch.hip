@@ -27,16 +27,39 @@ namespace sphfilt {
 
 // LDS of the largest worker: the staged shells of the fused worker
 // (ShellShape<128>::lds), which also covers the line scratch of every
-// theta/phi group, hybrid spectra included.
-constexpr int kBatchLds = ShellShape<128>::lds;
-template <int N>
+// theta/phi group, hybrid spectra included.  The instance that also takes
+// lines of 48, 96 and 192 points (R3) needs more for their hybrid spectra.
+template <int N, bool HYB>
+constexpr int batch_line_lds()
+{
+    return lines_per_256<N>() * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
+}
+template <bool HYB, bool R3>
+constexpr int batch_lds()
+{
+    constexpr int a = ShellShape<128>::lds;
+    constexpr int b = batch_line_lds<96, HYB>() > batch_line_lds<192, HYB>() ? batch_line_lds<96, HYB>()
+                                                                          : batch_line_lds<192, HYB>();
+    return R3 && b > a ? b : a;
+}
+template <int N, bool R3>
 constexpr bool batch_lds_fits()
 {
-    return kBatchLds >= lines_per_256<N>() * line_stride<Split<N>::N1, Split<N>::N2, true>();
+    return batch_lds<true, R3>() >= batch_line_lds<N, true>() &&
+           batch_lds<false, R3>() >= batch_line_lds<N, false>();
 }
-static_assert(batch_lds_fits<32>() && batch_lds_fits<64>() && batch_lds_fits<128>() &&
-                  batch_lds_fits<256>(),
+static_assert(batch_lds_fits<32, false>() && batch_lds_fits<64, false>() &&
+                  batch_lds_fits<128, false>() && batch_lds_fits<256, false>() &&
+                  batch_lds_fits<48, true>() && batch_lds_fits<96, true>() &&
+                  batch_lds_fits<192, true>(),
               "batch LDS holds every worker's line scratch");
+// Waves per SIMD the instances ask for.  The R3 instances take one: their
+// 24 values per lane need more than 256 registers, and the hybrid one's LDS
+// (a whole spectrum per line of 96 or 192) fits one workgroup per CU.
+template <bool HYB, bool R3>
+constexpr int oneshot_waves() { return R3 ? 1 : (HYB ? 2 : 1); }
+template <bool HYB, bool R3>
+constexpr int persistent_waves() { return R3 ? 1 : (HYB ? 1 : 2); }
 
 // Hybrid lines in a batch decide from their data; decisions are not recorded.
 __device__ __forceinline__ HybridArgs batch_hybrid(const BatchPatchDev &pd)
@@ -101,7 +124,7 @@ struct BatchArgs {
 
 // One work item k (workgroup-uniform): wait for its shells (second pass),
 // filter, signal its shells (first pass).
-template <bool HYB>
+template <bool HYB, bool R3>
 __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, double *lds,
                                          double *etab, int *flags)
 {
@@ -137,7 +160,18 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
         case 32: theta_item<32, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
         case 64: theta_item<64, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
         case 128: theta_item<128, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
-        default: theta_item<256, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+        default:
+            if constexpr (R3) {
+                switch (pd.n_line) {
+                case 48: theta_item<48, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+                case 96: theta_item<96, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+                case 192: theta_item<192, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+                default: theta_item<256, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+                }
+            } else {
+                theta_item<256, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane);
+            }
+            break;
         }
     } else if (w.pass == 2) {
         switch (pd.n_phi) {
@@ -150,7 +184,18 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
         case 32: phi_item<32, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
         case 64: phi_item<64, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
         case 128: phi_item<128, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
-        default: phi_item<256, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+        default:
+            if constexpr (R3) {
+                switch (pd.n_phi) {
+                case 48: phi_item<48, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+                case 96: phi_item<96, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+                case 192: phi_item<192, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+                default: phi_item<256, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+                }
+            } else {
+                phi_item<256, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane);
+            }
+            break;
         }
     }
 
@@ -186,15 +231,18 @@ __device__ __forceinline__ int next_ticket(int *ticket, int *cur)
 // The hybrid form needs a little more than 256 registers: two waves per SIMD
 // with a small spill (128 bytes per lane) beat one wave without (the hybrid
 // 64-patch batch: 2.05 against 2.64 ms).
-template <bool HYB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HYB ? 2 : 1))) void batch_kernel_oneshot(BatchArgs a)
+// R3: the instance that also takes lines of 48, 96 and 192 points (launched
+// only for batches that have such a patch; their 24 values per lane and
+// larger hybrid LDS would otherwise weigh on every batch).
+template <bool HYB, bool R3>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(oneshot_waves<HYB, R3>()))) void batch_kernel_oneshot(BatchArgs a)
 {
-    __shared__ double lds[kBatchLds];
+    __shared__ double lds[batch_lds<HYB, R3>()];
     __shared__ double etab[129];
     __shared__ int flags[64];
     __shared__ int cur;
     const int k = a.use_deps ? next_ticket(a.ticket, &cur) : (int)blockIdx.x;
-    if (k < a.n_work) run_item<HYB>(a, k, threadIdx.x, lds, etab, flags);
+    if (k < a.n_work) run_item<HYB, R3>(a, k, threadIdx.x, lds, etab, flags);
 }
 
 // Persistent form: a fixed grid; each workgroup takes tickets until the list
@@ -203,11 +251,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HYB ? 2 : 1
 // items (it would otherwise not fit in 256 registers).  The hybrid form, with
 // the detector and the mixed-pair mask, needs more than 256 registers; it runs
 // one wave per SIMD (at two it would spill 240 bytes per lane and lose a third).
-template <bool HYB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HYB ? 1 : 2))) void batch_kernel_persistent(
+template <bool HYB, bool R3>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_waves<HYB, R3>()))) void batch_kernel_persistent(
     BatchArgs a)
 {
-    __shared__ double lds[kBatchLds];
+    __shared__ double lds[batch_lds<HYB, R3>()];
     __shared__ double etab[129];
     __shared__ int flags[64];
     __shared__ int cur;
@@ -216,7 +264,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HYB ? 1 : 2
         if (k >= a.n_work) break;
         unsigned lane;
         asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((unsigned)threadIdx.x));
-        run_item<HYB>(a, k, (int)lane, lds, etab, flags);
+        run_item<HYB, R3>(a, k, (int)lane, lds, etab, flags);
     }
 }
 
@@ -247,27 +295,44 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
                         const double *const *ins, double *const *outs, const ThetaItem *th,
                         const PhiItem *ph, const double *fc, const int *shells, int *counters,
                         const int *need, int *ticket, int *error, const double *eneg, int use_deps,
-                        int spin_limit, int hybrid, hipStream_t s)
+                        int spin_limit, int variant, hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
     const BatchArgs a{work, n_work, patches, ins, outs, th, ph, fc, shells, counters,
                       need, ticket, error, eneg, use_deps, spin_limit};
-    if (grid <= 0) {
-        if (hybrid) batch_kernel_oneshot<true><<<n_work, 256, 0, s>>>(a);
-        else batch_kernel_oneshot<false><<<n_work, 256, 0, s>>>(a);
-    } else {
-        if (hybrid) batch_kernel_persistent<true><<<grid, 256, 0, s>>>(a);
-        else batch_kernel_persistent<false><<<grid, 256, 0, s>>>(a);
+    const bool one = grid <= 0;
+    const unsigned g = one ? (unsigned)n_work : (unsigned)grid;
+    switch (variant & 3) {
+    case 0:
+        if (one) batch_kernel_oneshot<false, false><<<g, 256, 0, s>>>(a);
+        else batch_kernel_persistent<false, false><<<g, 256, 0, s>>>(a);
+        break;
+    case kBatchHybrid:
+        if (one) batch_kernel_oneshot<true, false><<<g, 256, 0, s>>>(a);
+        else batch_kernel_persistent<true, false><<<g, 256, 0, s>>>(a);
+        break;
+    case kBatchRadix3:
+        if (one) batch_kernel_oneshot<false, true><<<g, 256, 0, s>>>(a);
+        else batch_kernel_persistent<false, true><<<g, 256, 0, s>>>(a);
+        break;
+    default:
+        if (one) batch_kernel_oneshot<true, true><<<g, 256, 0, s>>>(a);
+        else batch_kernel_persistent<true, true><<<g, 256, 0, s>>>(a);
+        break;
     }
     return hipGetLastError();
 }
 
-int batch_blocks_per_cu(int hybrid)
+int batch_blocks_per_cu(int variant)
 {
     int n = 0;
-    const hipError_t e =
-        hybrid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<true>, 256, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<false>, 256, 0);
+    hipError_t e;
+    switch (variant & 3) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<false, false>, 256, 0); break;
+    case kBatchHybrid: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<true, false>, 256, 0); break;
+    case kBatchRadix3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<false, true>, 256, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<true, true>, 256, 0); break;
+    }
     if (e != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }

@@ -48,14 +48,18 @@ hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n
                               int *error, hipStream_t s);
 // grid > 0: persistent form with `grid` workgroups; grid <= 0: one workgroup
 // per item.
+// Kernel instance of a batch: kBatchHybrid when some patch has a hybrid field
+// (the detector and mixed-pair mask), kBatchRadix3 when some patch has lines
+// of 48, 96 or 192 points.
+constexpr int kBatchHybrid = 1, kBatchRadix3 = 2;
 hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const BatchPatchDev *patches,
                         const double *const *ins, double *const *outs, const ThetaItem *th,
                         const PhiItem *ph, const double *fc, const int *shells, int *counters,
                         const int *need,
                         int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
-                        int hybrid, hipStream_t s);
-// Resident 256-lane workgroups of the persistent batch kernel per compute
-// unit (hybrid: the variant with the hybrid filter's detector).
-int batch_blocks_per_cu(int hybrid);
+                        int variant, hipStream_t s);
+// Resident 256-lane workgroups of the persistent batch kernel instance
+// `variant` per compute unit.
+int batch_blocks_per_cu(int variant);
 
 }  // namespace sphfilt

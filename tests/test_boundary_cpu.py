@@ -231,10 +231,7 @@ def test_batch_create_rejects_bad_patch(L, bad):
 
 def test_batch_create_unsupported_and_empty(L):
     assert _batch_create(L, [dict(), dict(n_theta=12)]) == L.EUNSUPPORTED
-    # lines of 48, 96 and 192 are plan-only
-    assert _batch_create(L, [dict(), dict(n_theta=48)]) == L.EUNSUPPORTED
-    assert _batch_create(L, [dict(n_phi=96), dict()]) == L.EUNSUPPORTED
-    assert _batch_create(L, [dict(n_theta=96, n_phi=192)]) == L.EUNSUPPORTED
+    assert _batch_create(L, [dict(), dict(n_phi=160)]) == L.EUNSUPPORTED
     h = ctypes.c_void_p()
     assert L.load().sphfilt_batch_create(ctypes.byref(h), 0, None, None) == L.EINVAL
 

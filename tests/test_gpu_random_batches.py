@@ -1,8 +1,8 @@
 """Seeded sweep over batches of random patches, against the oracle.
 
 Each case draws one to eight patches (theta-line and ring lengths among the
-supported ones, so patches with fused shells, with theta-idle shells and plain
-ones mix in one work list), per-field kinds including hybrid, parities,
+supported ones, radix-3 lengths included, so patches with fused shells, with
+theta-idle shells and plain ones mix in one work list), per-field kinds including hybrid, parities,
 cut-off scales over two decades, radius tables and floors; a schedule (one
 kernel with per-shell dependencies, two kernels, or two kernels with a
 parallel branch; one workgroup per item, or persistent with one or the most
@@ -19,7 +19,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
-LINES = (32, 64, 128, 256)
+LINES = (32, 48, 64, 96, 128, 192, 256)
 
 
 @pytest.fixture(scope="module")
