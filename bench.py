@@ -99,8 +99,9 @@ def parse():
                          "as JSON (for profiling the fused shell kernel)")
     ap.add_argument("--short-lines-only", action="store_true",
                     help="time only the dense short-line grids (n_phi = 32, 64, 128)")
-    ap.add_argument("--radix3-only", action="store_true",
-                    help="time only the 96 x 192 grid (lines with a radix-3 stage)")
+    ap.add_argument("--mixed-radix-only", action="store_true",
+                    help="time only the 96 x 192 and 80 x 160 grids (lines with a radix-3 or "
+                         "radix-5 stage)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -311,37 +312,42 @@ def bench_hybrid(torch, w, bufs, steps, stream):
             "algorithmic_bytes": st["bytes_forward_inplace"]}
 
 
-def bench_radix3(torch, steps, stream):
-    """Lines with a radix-3 stage: 24 fields x 128 shells x 96 x 192 (the
-    angular grid of the paper's FFT(96) black-hole run), rho = i + 1/2, at the
-    paper's cutoff cal-L = 2 (that run's value) and dense (every line
-    filtered, rho = 1, cal-L = 0.2): each pass and the forward filter in place."""
+def bench_mixed_radix(torch, steps, stream):
+    """Lines with a radix-3 or radix-5 stage, on the angular grids of the
+    paper's FFT(96) black-hole run (n_theta = 96, n_phi = 192: lines of 192,
+    cal-L = 2) and of its explosion test (n_theta = 80, n_phi = 160: lines of
+    160, cal-L = 4); 24 fields, rho = i + 1/2; at the paper's cutoff and dense
+    (every line filtered, rho = 1, cal-L = 0.2): each pass and the forward
+    filter in place."""
     import numpy as np
     from paper_2305_01537_amd.filter import Plan
-    F, R, T, P = 24, 128, 96, 192
-    g = torch.Generator(device="cuda").manual_seed(192)
-    x0 = torch.randn((F, R, T, P), dtype=torch.float64, device="cuda", generator=g)
-    bufs = [x0, x0.clone()]
-    parity = np.where(np.arange(F) % 3 == 2, -1, 1)
-    out = {"shape": [F, R, T, P]}
-    for name, L, rho in (("paper_cutoff", 2.0, None), ("dense", 0.2, np.ones(R))):
-        plan = Plan(R, T, P, F, parity=parity, L=L, rho=rho)
-        st = plan.stats()
-        ms_t = time_loop(torch, lambda b: plan.apply_theta(b, out=b), bufs, steps, 5, stream)
-        ms_p = time_loop(torch, lambda b: plan.apply_phi(b, out=b), bufs, steps, 5, stream)
-        ms_f = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 5, stream)
-        tb = 16 * st["theta_shells_active"] * T * P
-        pb = 16 * st["phi_rings_active"] * P
-        out[name] = {"cal_L": L, "forward_ms": ms_f,
-                     "points_per_s": st["n_points"] / (ms_f * 1e-3),
-                     "step_GBps": st["bytes_forward_inplace"] / (ms_f * 1e-3) / 1e9,
-                     "theta_GBps": tb / (ms_t * 1e-3) / 1e9 if tb else None,
-                     "phi_GBps": pb / (ms_p * 1e-3) / 1e9 if pb else None,
-                     "active_theta_shells": st["theta_shells_active"],
-                     "active_phi_rings": st["phi_rings_active"]}
-        plan.close()
-    del bufs, x0
-    torch.cuda.empty_cache()
+    out = {}
+    for grid, (F, R, T, P), L_paper in (("fft96_bh", (24, 128, 96, 192), 2.0),
+                                        ("explosion", (24, 160, 80, 160), 4.0)):
+        g = torch.Generator(device="cuda").manual_seed(P)
+        x0 = torch.randn((F, R, T, P), dtype=torch.float64, device="cuda", generator=g)
+        bufs = [x0, x0.clone()]
+        parity = np.where(np.arange(F) % 3 == 2, -1, 1)
+        res = {"shape": [F, R, T, P]}
+        for name, L, rho in (("paper_cutoff", L_paper, None), ("dense", 0.2, np.ones(R))):
+            plan = Plan(R, T, P, F, parity=parity, L=L, rho=rho)
+            st = plan.stats()
+            ms_t = time_loop(torch, lambda b: plan.apply_theta(b, out=b), bufs, steps, 5, stream)
+            ms_p = time_loop(torch, lambda b: plan.apply_phi(b, out=b), bufs, steps, 5, stream)
+            ms_f = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 5, stream)
+            tb = 16 * st["theta_shells_active"] * T * P
+            pb = 16 * st["phi_rings_active"] * P
+            res[name] = {"cal_L": L, "forward_ms": ms_f,
+                         "points_per_s": st["n_points"] / (ms_f * 1e-3),
+                         "step_GBps": st["bytes_forward_inplace"] / (ms_f * 1e-3) / 1e9,
+                         "theta_GBps": tb / (ms_t * 1e-3) / 1e9 if tb else None,
+                         "phi_GBps": pb / (ms_p * 1e-3) / 1e9 if pb else None,
+                         "active_theta_shells": st["theta_shells_active"],
+                         "active_phi_rings": st["phi_rings_active"]}
+            plan.close()
+        out[grid] = res
+        del bufs, x0
+        torch.cuda.empty_cache()
     return out
 
 
@@ -408,8 +414,8 @@ def main():
     if args.short_lines_only:
         print(json.dumps({"short_lines": bench_short_lines(torch, args.steps, stream)}), flush=True)
         return 0
-    if args.radix3_only:
-        print(json.dumps({"radix3": bench_radix3(torch, args.steps, stream)}), flush=True)
+    if args.mixed_radix_only:
+        print(json.dumps({"mixed_radix": bench_mixed_radix(torch, args.steps, stream)}), flush=True)
         return 0
 
     log("generating the share workload (24 x 256 x 128 x 256, FP64)")
@@ -517,9 +523,9 @@ def main():
         log("timing dense short-line grids")
         extra["short_lines"] = bench_short_lines(torch, max(10, args.steps // 2), stream)
         log(f"short lines: {extra['short_lines']}")
-        log("timing radix-3 lines (96 x 192)")
-        extra["radix3"] = bench_radix3(torch, max(10, args.steps // 2), stream)
-        log(f"radix-3 lines: {extra['radix3']}")
+        log("timing radix-3 and radix-5 lines (96 x 192, 80 x 160)")
+        extra["mixed_radix"] = bench_mixed_radix(torch, max(10, args.steps // 2), stream)
+        log(f"mixed-radix lines: {extra['mixed_radix']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -235,6 +235,7 @@ void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
 
 // Lines of 48, 96 or 192 points take the batch kernel's radix-3 instance.
 bool radix3_line(int n) { return n == 48 || n == 96 || n == 192; }
+bool radix5_line(int n) { return n == 80 || n == 160; }
 
 // A patch whose theta-filtered shells are all fused (n_phi = 2 n_theta <= 128,
 // see build_items) runs entirely in the first pass: groups of whole shells
@@ -610,6 +611,8 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
         const sphfilt_patch_desc &d = desc[p];
         const int rc = validate(d.n_r, d.n_theta, d.n_phi, d.n_fields, d.parity, &d.cut);
         if (rc) return rc;
+        // lines of 80 and 160 points (40 values per lane at 160) are plan-only
+        if (radix5_line(2 * d.n_theta) || radix5_line(d.n_phi)) return SPHFILT_EUNSUPPORTED;
         shells += (long long)d.n_fields * d.n_r;
     }
     if (shells > 0x7fffffffLL) return SPHFILT_EUNSUPPORTED;

@@ -116,42 +116,64 @@ __device__ __forceinline__ cplx twiddle_const(cplx a)
     }
 }
 
-// cos(a pi / 12) for a in [0, 6] ((sqrt6 +- sqrt2)/4, sqrt3/2, sqrt2/2, 1/2),
-// to 25 digits; and for any integer a by the quadrant symmetries.
-constexpr double cos_pi12_q(int a)
+// cos(a pi / D) for D = 12 (a in [0, 6]: (sqrt6 +- sqrt2)/4, sqrt3/2,
+// sqrt2/2, 1/2) and D = 20 (a in [0, 10]), to 25 digits; any integer a by the
+// quadrant symmetries.  The twiddles of the transforms whose size divides 24
+// or 40.
+template <int D>
+constexpr double cos_frac_q(int a)
 {
-    return a == 0   ? 1.0
-           : a == 1 ? 0.9659258262890682867497432
-           : a == 2 ? 0.8660254037844386467637232
-           : a == 3 ? 0.7071067811865475244008444
-           : a == 4 ? 0.5
-           : a == 5 ? 0.2588190451025207623488988
-                    : 0.0;
+    if constexpr (D == 12) {
+        return a == 0   ? 1.0
+               : a == 1 ? 0.9659258262890682867497432
+               : a == 2 ? 0.8660254037844386467637232
+               : a == 3 ? 0.7071067811865475244008444
+               : a == 4 ? 0.5
+               : a == 5 ? 0.2588190451025207623488988
+                        : 0.0;
+    } else {
+        static_assert(D == 20, "tables for pi/12 and pi/20");
+        return a == 0   ? 1.0
+               : a == 1 ? 0.9876883405951377261900402
+               : a == 2 ? 0.9510565162951535721164393
+               : a == 3 ? 0.8910065241883678623597096
+               : a == 4 ? 0.8090169943749474241022934
+               : a == 5 ? 0.7071067811865475244008444
+               : a == 6 ? 0.5877852522924731291687060
+               : a == 7 ? 0.4539904997395467915604084
+               : a == 8 ? 0.3090169943749474241022934
+               : a == 9 ? 0.1564344650402308690101053
+                        : 0.0;
+    }
 }
-constexpr double cos_pi12(int a)
+template <int D>
+constexpr double cos_frac(int a)
 {
-    a = ((a % 24) + 24) % 24;
-    return a <= 6 ? cos_pi12_q(a) : a <= 12 ? -cos_pi12_q(12 - a) : a <= 18 ? -cos_pi12_q(a - 12) : cos_pi12_q(24 - a);
+    a = ((a % (2 * D)) + 2 * D) % (2 * D);
+    return a <= D / 2 ? cos_frac_q<D>(a)
+           : a <= D   ? -cos_frac_q<D>(D - a)
+           : a <= 3 * D / 2 ? -cos_frac_q<D>(a - D)
+                            : cos_frac_q<D>(2 * D - a);
 }
-constexpr double sin_pi12(int a) { return cos_pi12(6 - a); }
+template <int D>
+constexpr double sin_frac(int a) { return cos_frac<D>(D / 2 - a); }
 
-// a * exp(-i A pi / 12) (forward) or exp(+i A pi / 12) (INV): the twiddles of
-// the transforms whose size divides 24.
-template <int A, bool INV>
-__device__ __forceinline__ cplx twiddle_pi12(cplx a)
+// a * exp(-i A pi / D) (forward) or exp(+i A pi / D) (INV).
+template <int D, int A, bool INV>
+__device__ __forceinline__ cplx twiddle_frac(cplx a)
 {
-    constexpr int a0 = ((A % 24) + 24) % 24;
-    constexpr int e = INV ? a0 : (24 - a0) % 24;         // exp(i e pi / 12)
+    constexpr int a0 = ((A % (2 * D)) + 2 * D) % (2 * D);
+    constexpr int e = INV ? a0 : (2 * D - a0) % (2 * D);   // exp(i e pi / D)
     if constexpr (e == 0) {
         return a;
-    } else if constexpr (e == 12) {
+    } else if constexpr (e == D) {
         return {-a.re, -a.im};
-    } else if constexpr (e == 6) {
+    } else if constexpr (2 * e == D) {
         return {-a.im, a.re};
-    } else if constexpr (e == 18) {
+    } else if constexpr (2 * e == 3 * D) {
         return {a.im, -a.re};
     } else {
-        constexpr double c = cos_pi12(e), s = sin_pi12(e);
+        constexpr double c = cos_frac<D>(e), s = sin_frac<D>(e);
         return {a.re * c - a.im * s, a.re * s + a.im * c};
     }
 }
@@ -171,36 +193,71 @@ __device__ __forceinline__ void dft3(cplx &x0, cplx &x1, cplx &x2)
     x2 = csub(m, j);
 }
 
+// 5-point DFT in place.  With W = exp(-2 pi i / 5), c1 = cos(2pi/5),
+// c2 = cos(4pi/5), s1 = sin(2pi/5), s2 = sin(4pi/5), u1 = x1 + x4,
+// u2 = x2 + x3, d1 = x1 - x4, d2 = x2 - x3 (W^4 = conj W, W^3 = conj W^2):
+//   X0 = x0 + u1 + u2
+//   X1, X4 = x0 + c1 u1 + c2 u2 -+ i (s1 d1 + s2 d2)
+//   X2, X3 = x0 + c2 u1 + c1 u2 -+ i (s2 d1 - s1 d2)
+// (forward; INV swaps the signs of the i terms).
+template <bool INV>
+__device__ __forceinline__ void dft5(cplx &x0, cplx &x1, cplx &x2, cplx &x3, cplx &x4)
+{
+    constexpr double c1 = 0.3090169943749474241022934, c2 = -0.8090169943749474241022934;
+    constexpr double s1 = 0.9510565162951535721164393, s2 = 0.5877852522924731291687060;
+    const cplx u1 = cadd(x1, x4), u2 = cadd(x2, x3), d1 = csub(x1, x4), d2 = csub(x2, x3);
+    const cplx a1 = {x0.re + c1 * u1.re + c2 * u2.re, x0.im + c1 * u1.im + c2 * u2.im};
+    const cplx a2 = {x0.re + c2 * u1.re + c1 * u2.re, x0.im + c2 * u1.im + c1 * u2.im};
+    const cplx b1 = {s1 * d1.re + s2 * d2.re, s1 * d1.im + s2 * d2.im};
+    const cplx b2 = {s2 * d1.re - s1 * d2.re, s2 * d1.im - s1 * d2.im};
+    // -i b = (b.im, -b.re); +i b = (-b.im, b.re)
+    const cplx j1 = INV ? cplx{-b1.im, b1.re} : cplx{b1.im, -b1.re};
+    const cplx j2 = INV ? cplx{-b2.im, b2.re} : cplx{b2.im, -b2.re};
+    x0 = cadd(x0, cadd(u1, u2));
+    x1 = cadd(a1, j1);
+    x4 = csub(a1, j1);
+    x2 = cadd(a2, j2);
+    x3 = csub(a2, j2);
+}
+
 // In-register DFT of size R on v[OFF + STRIDE*i], i in [0, R): natural order
 // in, natural order out.  Forward: exp(-2 pi i n k / R); INV: exp(+...),
-// unnormalised.  R is a power of two up to 64, or 3 times a power of two
-// dividing 24 (R = 3, 6, 12, 24): then, with R = 3 B, n = b + B a and
-// k = ka + 3 kb,
-//   X[ka + 3 kb] = sum_b W_B^{b kb} W_R^{b ka} sum_a x[b + B a] W_3^{a ka},
-// i.e. 3-point DFTs over a, twiddles W_R^{b ka}, B-point DFTs over b, and a
+// unnormalised.  R is a power of two up to 64, or P = 3 or 5 times a power of
+// two B with R dividing 24 (P = 3) or 40 (P = 5): then, with n = b + B a and
+// k = ka + P kb,
+//   X[ka + P kb] = sum_b W_B^{b kb} W_R^{b ka} sum_a x[b + B a] W_P^{a ka},
+// i.e. P-point DFTs over a, twiddles W_R^{b ka}, B-point DFTs over b, and a
 // register renaming to natural order.
 template <int R, bool INV, int OFF = 0, int STRIDE = 1, int NV>
 __device__ __forceinline__ void dft_reg(cplx (&v)[NV])
 {
-    if constexpr (R % 3 == 0) {
-        static_assert(24 % R == 0, "a radix-3 transform size must divide 24");
-        constexpr int B = R / 3;
+    if constexpr (R % 3 == 0 || R % 5 == 0) {
+        constexpr int P = R % 3 == 0 ? 3 : 5, D = P == 3 ? 12 : 20;
+        static_assert((2 * D) % R == 0, "an odd-radix transform size must divide 24 or 40");
+        constexpr int B = R / P;
         static_for<0, B>([&](auto bb) {
             constexpr int b = decltype(bb)::value;
-            constexpr int p0 = OFF + STRIDE * b, p1 = p0 + STRIDE * B, p2 = p1 + STRIDE * B;
-            dft3<INV>(v[p0], v[p1], v[p2]);
-            // W_R^{b ka} = exp(-+ i (24 / R) b ka pi / 12)
-            v[p1] = twiddle_pi12<(24 / R) * b, INV>(v[p1]);
-            v[p2] = twiddle_pi12<(24 / R) * 2 * b, INV>(v[p2]);
+            constexpr int p0 = OFF + STRIDE * b;
+            if constexpr (P == 3) {
+                dft3<INV>(v[p0], v[p0 + STRIDE * B], v[p0 + 2 * STRIDE * B]);
+            } else {
+                dft5<INV>(v[p0], v[p0 + STRIDE * B], v[p0 + 2 * STRIDE * B], v[p0 + 3 * STRIDE * B],
+                          v[p0 + 4 * STRIDE * B]);
+            }
+            // W_R^{b ka} = exp(-+ i (2 D / R) b ka pi / D)
+            static_for<1, P>([&](auto kk) {
+                constexpr int ka = decltype(kk)::value;
+                v[p0 + ka * STRIDE * B] = twiddle_frac<D, (2 * D / R) * b * ka, INV>(v[p0 + ka * STRIDE * B]);
+            });
         });
-        static_for<0, 3>([&](auto aa) {
+        static_for<0, P>([&](auto aa) {
             dft_reg<B, INV, OFF + STRIDE * B * decltype(aa)::value, STRIDE>(v);
         });
-        // X[ka + 3 kb] sits at position ka B + kb
+        // X[ka + P kb] sits at position ka B + kb
         cplx tmp[R];
         static_for<0, R>([&](auto kk) {
             constexpr int k = decltype(kk)::value;
-            tmp[k] = v[OFF + STRIDE * ((k % 3) * B + k / 3)];
+            tmp[k] = v[OFF + STRIDE * ((k % P) * B + k / P)];
         });
         static_for<0, R>([&](auto kk) {
             constexpr int k = decltype(kk)::value;
@@ -208,9 +265,9 @@ __device__ __forceinline__ void dft_reg(cplx (&v)[NV])
         });
         return;
     }
-    static_assert(R % 3 == 0 || ((R & (R - 1)) == 0 && R >= 1 && R <= 64),
+    static_assert(R % 3 == 0 || R % 5 == 0 || ((R & (R - 1)) == 0 && R >= 1 && R <= 64),
                   "radix must be a power of two <= 64");
-    if constexpr (R > 1 && R % 3 != 0) {
+    if constexpr (R > 1 && R % 3 != 0 && R % 5 != 0) {
         // decimation in frequency: spans R/2, R/4, ..., 1; output bit-reversed
         static_for<0, ilog2(R)>([&](auto st) {
             constexpr int span = R >> (decltype(st)::value + 1);

@@ -22,7 +22,8 @@ bool fault(const char *what)
 
 bool supported_line(int n)
 {
-    return n == 32 || n == 48 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256;
+    return n == 32 || n == 48 || n == 64 || n == 80 || n == 96 || n == 128 || n == 160 ||
+           n == 192 || n == 256;
 }
 
 // cos and sin of 2 pi j / N, reducing the angle to the first octant with

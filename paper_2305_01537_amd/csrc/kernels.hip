@@ -16,15 +16,16 @@ namespace sphfilt {
 // Waves per SIMD a pass kernel asks the compiler for (it caps the registers
 // per lane at 512 / waves).  The hybrid-capable instances: two, where two
 // workgroups' line scratch (a whole spectrum per line) fits in LDS, else one
-// (lines of 96 and 192 at 256 lanes).  The plain instances at N = 192: two
-// as well, for a 4-12 register spill; they would otherwise take a little over
-// 256 registers and run one wave.  The other plain instances: no target
-// (they fit two or more waves by themselves).
+// (lines of 96, 160 and 192 at 256 lanes).  The plain instances at N = 192:
+// two as well, for a 4-12 register spill; they would otherwise take a little
+// over 256 registers and run one wave.  At N = 160 (40 values per lane) both
+// forms need 330 or more registers and take one wave.  The other plain
+// instances: no target (they fit two or more waves by themselves).
 template <int N, int LINES, bool HYB>
 constexpr int pass_waves()
 {
     constexpr int bytes = 8 * LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
-    return (HYB || N == 192) && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
+    return N != 160 && (HYB || N == 192) && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
 }
 
 // theta-pass: workgroup b handles shell group g = b / tiles (S = C / cp shells
@@ -101,8 +102,10 @@ int lanes_per_line(int n_line)
     case 32: return Split<32>::N2;
     case 48: return Split<48>::N2;
     case 64: return Split<64>::N2;
+    case 80: return Split<80>::N2;
     case 96: return Split<96>::N2;
     case 128: return Split<128>::N2;
+    case 160: return Split<160>::N2;
     case 192: return Split<192>::N2;
     case 256: return Split<256>::N2;
     default: return 0;
@@ -118,6 +121,7 @@ int ilog2_int(int v)
 
 int theta_lines_per_group(int n_line)
 {
+    if (n_line == 160) return theta_lines<160>();
     return lanes_per_line(n_line) ? 256 / lanes_per_line(n_line) : 0;
 }
 
@@ -132,8 +136,13 @@ int default_theta_cols(int n_line, int n_phi)
     return cols;
 }
 
+// At N = 160 a phi workgroup takes at most 32 ring pairs (the hybrid
+// spectra of 64 would not fit in LDS).
+constexpr int kMaxPhiLines160 = 32;
+
 int default_phi_lines(int n_line)
 {
+    if (n_line == 160) return kMaxPhiLines160;
     return lanes_per_line(n_line) ? 256 / lanes_per_line(n_line) : 0;
 }
 
@@ -148,7 +157,7 @@ bool phi_shape_ok(int n_line, int lines)
 {
     const int l = lanes_per_line(n_line);
     return l > 0 && (lines == 4 || lines == 8 || lines == 16 || lines == 32 || lines == 64) &&
-           l * lines <= 256 && l * lines >= 16;
+           l * lines <= 256 && l * lines >= 16 && (n_line != 160 || lines <= kMaxPhiLines160);
 }
 
 // ---------------------------------------------------------------------------
@@ -159,12 +168,12 @@ static hipError_t theta_go(int cols, const double *in, double *out, const ThetaI
                            int n_items, int n_theta, int n_phi, const Twiddle *tw,
                            const double *eneg, const HybridArgs &h, hipStream_t s)
 {
-    constexpr int C = lines_per_256<N>();
+    constexpr int C = theta_lines<N>();
     const int cp_log2 = ilog2_int(cols);
     const int per_group = C / cols;
     const int tiles = (n_phi / 2) / (2 * cols);
     const int groups = (n_items + per_group - 1) / per_group;
-    const dim3 grid((unsigned)(groups * tiles)), block(256);
+    const dim3 grid((unsigned)(groups * tiles)), block(C * Split<N>::N2);
     // the hybrid-capable variant only when the plan has hybrid fields: its
     // detector and two-kind mask cost registers the plain filter does not need
     if (h.present)
@@ -187,8 +196,10 @@ hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
     case 32: return theta_go<32>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 48: return theta_go<48>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 64: return theta_go<64>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
+    case 80: return theta_go<80>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 96: return theta_go<96>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 128: return theta_go<128>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
+    case 160: return theta_go<160>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 192: return theta_go<192>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     case 256: return theta_go<256>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
     default: return hipErrorInvalidValue;
@@ -200,7 +211,8 @@ static hipError_t phi_go(const double *in, double *out, const PhiItem *items, in
                          int n_theta, const Twiddle *tw, const double *eneg, const HybridArgs &h,
                          hipStream_t s)
 {
-    if constexpr (LINES * Split<N>::N2 > 256 || LINES * Split<N>::N2 < 16) {
+    if constexpr (LINES * Split<N>::N2 > 256 || LINES * Split<N>::N2 < 16 ||
+                  (N == 160 && LINES > kMaxPhiLines160)) {
         return hipErrorInvalidValue;
     } else {
         const dim3 grid((unsigned)((n_items + LINES - 1) / LINES)), block(LINES * Split<N>::N2);
@@ -239,8 +251,10 @@ hipError_t launch_phi(int n_line, int lines, const double *in, double *out, cons
     case 32: return phi_lines<32>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 48: return phi_lines<48>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 64: return phi_lines<64>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
+    case 80: return phi_lines<80>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 96: return phi_lines<96>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 128: return phi_lines<128>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
+    case 160: return phi_lines<160>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 192: return phi_lines<192>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     case 256: return phi_lines<256>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
     default: return hipErrorInvalidValue;

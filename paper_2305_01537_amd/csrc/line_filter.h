@@ -309,13 +309,16 @@ __device__ __forceinline__ void stage_exp_table(double *etab, const double *__re
 
 // N = N1 * N2: N2 lanes per line, N1 values per lane; N2 divides N1 (the
 // transpose gives each lane N1 / N2 whole second-stage transforms).  The
-// lengths 48, 96 and 192 take a radix-3 stage in the N1-point transform.
+// lengths 48, 96 and 192 take a radix-3 stage in the N1-point transform, 80
+// and 160 a radix-5 stage.
 template <int N> struct Split;
 template <> struct Split<32>  { static constexpr int N1 = 8,  N2 = 4; };
 template <> struct Split<48>  { static constexpr int N1 = 12, N2 = 4; };
 template <> struct Split<64>  { static constexpr int N1 = 8,  N2 = 8; };
+template <> struct Split<80>  { static constexpr int N1 = 20, N2 = 4; };
 template <> struct Split<96>  { static constexpr int N1 = 24, N2 = 4; };
 template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
+template <> struct Split<160> { static constexpr int N1 = 40, N2 = 4; };
 template <> struct Split<192> { static constexpr int N1 = 24, N2 = 8; };
 template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
 
@@ -394,6 +397,11 @@ __device__ __forceinline__ void hybrid_kinds(const cplx (&v)[N1], int t, double 
 // Lanes per line and lines per 256-lane workgroup for each supported N.
 template <int N>
 constexpr int lines_per_256() { return 256 / Split<N>::N2; }
+// Lines per workgroup of the per-plan theta kernel: 256 lanes, except at
+// N = 160, where 64 lines' hybrid spectra (2N + 1 doubles each) would not fit
+// in LDS: 32 lines on 128 lanes.
+template <int N>
+constexpr int theta_lines() { return N == 160 ? 32 : lines_per_256<N>(); }
 
 // ---------------------------------------------------------------------------
 // theta-pass worker.  C complex lines per workgroup (C * N2 lanes, lane
@@ -415,7 +423,7 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
                                             double *etab, int *flags, const HybridArgs &h, int lane)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-    static_assert(C * N2 == 256, "theta workgroups have 256 lanes");
+    static_assert(C * N2 <= 256 && 256 % (C * N2) == 0, "theta workgroups have 128 or 256 lanes");
     const int p = lane % C, t = lane / C;
     const int u = p >> cp_log2, pp = p & ((1 << cp_log2) - 1);
     const bool valid = u < n_valid;

@@ -83,7 +83,10 @@ def test_grmhd_slice(torch_gpu, L):
                                            (64, 256), (128, 256), (128, 64), (16, 256), (128, 32),
                                            # lines with a radix-3 stage (48, 96, 192)
                                            (24, 48), (48, 96), (96, 192), (96, 128), (64, 192),
-                                           (24, 256), (128, 96), (16, 48), (96, 32), (48, 192)])
+                                           (24, 256), (128, 96), (16, 48), (96, 32), (48, 192),
+                                           # and with a radix-5 stage (80, 160)
+                                           (80, 160), (40, 80), (80, 64), (40, 160), (128, 80),
+                                           (16, 160), (96, 80)])
 def test_every_supported_size(torch_gpu, n_theta, n_phi):
     rng = np.random.default_rng(n_theta * 1000 + n_phi)
     shape = (3, 5, n_theta, n_phi)
@@ -200,9 +203,9 @@ def test_share_full_size_sampled_shells(torch_gpu):
         plan.close()
 
 
-@pytest.mark.parametrize("n_theta,n_phi", [(96, 192), (48, 96), (24, 48)])
+@pytest.mark.parametrize("n_theta,n_phi", [(96, 192), (48, 96), (24, 48), (80, 160), (40, 80)])
 def test_radix3_grid_schedules_and_hybrid(torch_gpu, n_theta, n_phi):
-    """Lines with a radix-3 stage: every theta tile that divides the meridian
+    """Lines with a radix-3 or radix-5 stage: every theta tile that divides the meridian
     pairs and every phi launch shape give results within rounding of each
     other (the phi shape bitwise) and of the oracle; hybrid fields too."""
     torch = torch_gpu

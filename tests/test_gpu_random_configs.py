@@ -1,7 +1,7 @@
 """Seeded sweep over plan configurations, against the oracle.
 
 Each case draws a grid (2 n_theta and n_phi among the supported line lengths,
-radix-3 ones included, so grids with fused shells, with overlapped passes and
+radix-3 and radix-5 ones included, so grids with fused shells, with overlapped passes and
 plain ones all occur),
 per-field kinds (exponential, Gaussian, sharp, hybrid) and parities, cut-off
 scales over two decades, a radius table (uniform, stretched or None), a floor,
@@ -17,7 +17,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
-LINES = (32, 48, 64, 96, 128, 192, 256)
+LINES = (32, 48, 64, 80, 96, 128, 160, 192, 256)
 
 
 @pytest.fixture(scope="module")

@@ -235,7 +235,7 @@ def test_p2_high_m_is_damped_near_poles(oracle_mod):
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", [EXP, GAUSS, SHARP])
 @pytest.mark.parametrize("s", [1, -1])
-@pytest.mark.parametrize("T,P", [(16, 32), (24, 48), (48, 96)])
+@pytest.mark.parametrize("T,P", [(16, 32), (24, 48), (48, 96), (40, 80)])
 def test_p3_separable_eigenmodes(oracle_mod, kind, s, T, P):
     R = 3
     rho = np.array([0.5, 1.5, 4.5])
@@ -430,9 +430,10 @@ def test_p10_library_fft_matches(oracle_mod, kind):
         assert rel_err(oracle_mod.adjoint(w.x, parity=w.parity, rho=w.rho, L=L, kind=kind), refa) <= 1e-13
 
 
-@pytest.mark.parametrize("T,P", [(96, 192), (48, 96), (24, 48)])
+@pytest.mark.parametrize("T,P", [(96, 192), (48, 96), (24, 48), (80, 160), (40, 80)])
 def test_p10_library_fft_matches_radix3_lengths(oracle_mod, T, P):
-    # lines of 3 * 2^k points: numpy's FFT against the oracle's direct DFTs
+    # lines of 3 * 2^k and 5 * 2^k points: numpy's FFT against the oracle's
+    # direct DFTs
     rng = np.random.default_rng(T)
     x = rng.standard_normal((2, 3, T, P))
     parity = np.array([1, -1])
