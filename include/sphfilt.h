@@ -36,8 +36,8 @@
  *
  * Supported sizes: 2*n_theta and n_phi each in
  * {32, 48, 64, 80, 96, 128, 160, 192, 256} (48, 96 and 192 are transformed
- * with a radix-3 stage, 80 and 160 with a radix-5 stage); batches take all
- * but 80 and 160.  Other sizes return SPHFILT_EUNSUPPORTED.
+ * with a radix-3 stage, 80 and 160 with a radix-5 stage).  Other sizes
+ * return SPHFILT_EUNSUPPORTED.
  */
 #ifndef SPHFILT_H
 #define SPHFILT_H
@@ -201,8 +201,7 @@ int sphfilt_workload_stats(int n_r, int n_theta, int n_phi, int n_fields, const 
  *               meridian pairs theta_cols apart share one complex transform,
  *               so changing it changes round-off only.  0 keeps the value.
  *   phi_lines   ring pairs per workgroup of the phi kernel: 4, 8, 16, 32 or
- *               64 (at most 256 lanes per workgroup; at most 32 for
- *               n_phi = 160).  0 keeps the value.
+ *               64 (at most 256 lanes per workgroup).  0 keeps the value.
  * Returns SPHFILT_EINVAL for other values.  Not thread-safe against
  * concurrent apply calls on the same plan.
  */
@@ -274,11 +273,11 @@ typedef struct {
 /*
  * Create a batch of n_patches patches on the current HIP device.
  *   desc             [n_patches] patch descriptions; validated like
- *                    sphfilt_plan_create (same error codes); lines of 80 or
- *                    160 points are SPHFILT_EUNSUPPORTED here.  A batch with
- *                    a line of 48, 96 or 192 points runs a kernel instance
- *                    that carries those lengths too (one wave per SIMD).
- *                    Read during the call only.
+ *                    sphfilt_plan_create (same error codes).  A batch with
+ *                    a line that is not a power of two (48, 80, 96, 160 or
+ *                    192 points) runs a kernel instance that carries those
+ *                    lengths too (one wave per SIMD).  Read during the call
+ *                    only.
  *   tune_cache_path  NULL: use the default schedule (no tuning).  Otherwise
  *                    a JSON file: if it holds a schedule for this set of
  *                    patches on this GPU architecture, that schedule is used;

@@ -233,9 +233,9 @@ void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
     }
 }
 
-// Lines of 48, 96 or 192 points take the batch kernel's radix-3 instance.
-bool radix3_line(int n) { return n == 48 || n == 96 || n == 192; }
-bool radix5_line(int n) { return n == 80 || n == 160; }
+// Lines that are not powers of two (48, 80, 96, 160, 192) take the batch
+// kernel's second instance.
+bool mixed_radix_line(int n) { return (n & (n - 1)) != 0; }
 
 // A patch whose theta-filtered shells are all fused (n_phi = 2 n_theta <= 128,
 // see build_items) runs entirely in the first pass: groups of whole shells
@@ -611,8 +611,6 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
         const sphfilt_patch_desc &d = desc[p];
         const int rc = validate(d.n_r, d.n_theta, d.n_phi, d.n_fields, d.parity, &d.cut);
         if (rc) return rc;
-        // lines of 80 and 160 points (40 values per lane at 160) are plan-only
-        if (radix5_line(2 * d.n_theta) || radix5_line(d.n_phi)) return SPHFILT_EUNSUPPORTED;
         shells += (long long)d.n_fields * d.n_r;
     }
     if (shells > 0x7fffffffLL) return SPHFILT_EUNSUPPORTED;
@@ -663,13 +661,13 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
             bool r3 = false;
             for (int p = 0; p < n_patches; ++p) {
                 b->hybrid |= hybrid_args(&desc[p].cut, desc[p].n_fields).present;
-                r3 = r3 || radix3_line(2 * desc[p].n_theta) || radix3_line(desc[p].n_phi);
+                r3 = r3 || mixed_radix_line(2 * desc[p].n_theta) || mixed_radix_line(desc[p].n_phi);
             }
             b->variant = (b->hybrid ? kBatchHybrid : 0) | (r3 ? kBatchRadix3 : 0);
             b->max_wpc = batch_blocks_per_cu(b->variant);
             b->signature = signature(b->arch, n_patches, desc);
         }
-        for (int N : {32, 48, 64, 96, 128, 192, 256}) {
+        for (int N : {32, 48, 64, 80, 96, 128, 160, 192, 256}) {
             if (rc) break;
             bool used = false;
             for (const PatchHost &h : b->patches) used |= (2 * h.n_theta == N) || (h.n_phi == N);

@@ -28,7 +28,8 @@ namespace sphfilt {
 // LDS of the largest worker: the staged shells of the fused worker
 // (ShellShape<128>::lds), which also covers the line scratch of every
 // theta/phi group, hybrid spectra included.  The instance that also takes
-// lines of 48, 96 and 192 points (R3) needs more for their hybrid spectra.
+// the lengths that are not powers of two (48, 80, 96, 160, 192: R3) needs
+// more for their hybrid spectra.
 template <int N, bool HYB>
 constexpr int batch_line_lds()
 {
@@ -50,7 +51,8 @@ constexpr bool batch_lds_fits()
 }
 static_assert(batch_lds_fits<32, false>() && batch_lds_fits<64, false>() &&
                   batch_lds_fits<128, false>() && batch_lds_fits<256, false>() &&
-                  batch_lds_fits<48, true>() && batch_lds_fits<96, true>() &&
+                  batch_lds_fits<48, true>() && batch_lds_fits<80, true>() &&
+                  batch_lds_fits<96, true>() && batch_lds_fits<160, true>() &&
                   batch_lds_fits<192, true>(),
               "batch LDS holds every worker's line scratch");
 // Waves per SIMD the instances ask for.  The R3 instances take one: their
@@ -164,7 +166,9 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
             if constexpr (R3) {
                 switch (pd.n_line) {
                 case 48: theta_item<48, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+                case 80: theta_item<80, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
                 case 96: theta_item<96, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
+                case 160: theta_item<160, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
                 case 192: theta_item<192, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
                 default: theta_item<256, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
                 }
@@ -188,7 +192,9 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
             if constexpr (R3) {
                 switch (pd.n_phi) {
                 case 48: phi_item<48, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+                case 80: phi_item<80, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
                 case 96: phi_item<96, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
+                case 160: phi_item<160, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
                 case 192: phi_item<192, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
                 default: phi_item<256, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
                 }
@@ -231,9 +237,9 @@ __device__ __forceinline__ int next_ticket(int *ticket, int *cur)
 // The hybrid form needs a little more than 256 registers: two waves per SIMD
 // with a small spill (128 bytes per lane) beat one wave without (the hybrid
 // 64-patch batch: 2.05 against 2.64 ms).
-// R3: the instance that also takes lines of 48, 96 and 192 points (launched
-// only for batches that have such a patch; their 24 values per lane and
-// larger hybrid LDS would otherwise weigh on every batch).
+// R3: the instance that also takes lines of 48, 80, 96, 160 and 192 points
+// (launched only for batches that have such a patch; their 20-24 values per
+// lane and larger hybrid LDS would otherwise weigh on every batch).
 template <bool HYB, bool R3>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(oneshot_waves<HYB, R3>()))) void batch_kernel_oneshot(BatchArgs a)
 {

@@ -50,7 +50,7 @@ hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n
 // per item.
 // Kernel instance of a batch: kBatchHybrid when some patch has a hybrid field
 // (the detector and mixed-pair mask), kBatchRadix3 when some patch has lines
-// of 48, 96 or 192 points.
+// that are not powers of two (48, 80, 96, 160 or 192 points).
 constexpr int kBatchHybrid = 1, kBatchRadix3 = 2;
 hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const BatchPatchDev *patches,
                         const double *const *ins, double *const *outs, const ThetaItem *th,

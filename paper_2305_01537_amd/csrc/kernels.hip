@@ -16,16 +16,15 @@ namespace sphfilt {
 // Waves per SIMD a pass kernel asks the compiler for (it caps the registers
 // per lane at 512 / waves).  The hybrid-capable instances: two, where two
 // workgroups' line scratch (a whole spectrum per line) fits in LDS, else one
-// (lines of 96, 160 and 192 at 256 lanes).  The plain instances at N = 192:
-// two as well, for a 4-12 register spill; they would otherwise take a little
-// over 256 registers and run one wave.  At N = 160 (40 values per lane) both
-// forms need 330 or more registers and take one wave.  The other plain
-// instances: no target (they fit two or more waves by themselves).
+// (lines of 96, 160 and 192 at 256 lanes).  The plain instances with 24
+// values per lane (N = 160, 192): two as well, for a small spill; they would
+// otherwise take a little over 256 registers and run one wave.  The other
+// plain instances: no target (they fit two or more waves by themselves).
 template <int N, int LINES, bool HYB>
 constexpr int pass_waves()
 {
     constexpr int bytes = 8 * LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
-    return N != 160 && (HYB || N == 192) && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
+    return (HYB || Split<N>::NV == 24 && Split<N>::N2 == 8) && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
 }
 
 // theta-pass: workgroup b handles shell group g = b / tiles (S = C / cp shells
@@ -121,7 +120,6 @@ int ilog2_int(int v)
 
 int theta_lines_per_group(int n_line)
 {
-    if (n_line == 160) return theta_lines<160>();
     return lanes_per_line(n_line) ? 256 / lanes_per_line(n_line) : 0;
 }
 
@@ -136,13 +134,8 @@ int default_theta_cols(int n_line, int n_phi)
     return cols;
 }
 
-// At N = 160 a phi workgroup takes at most 32 ring pairs (the hybrid
-// spectra of 64 would not fit in LDS).
-constexpr int kMaxPhiLines160 = 32;
-
 int default_phi_lines(int n_line)
 {
-    if (n_line == 160) return kMaxPhiLines160;
     return lanes_per_line(n_line) ? 256 / lanes_per_line(n_line) : 0;
 }
 
@@ -157,7 +150,7 @@ bool phi_shape_ok(int n_line, int lines)
 {
     const int l = lanes_per_line(n_line);
     return l > 0 && (lines == 4 || lines == 8 || lines == 16 || lines == 32 || lines == 64) &&
-           l * lines <= 256 && l * lines >= 16 && (n_line != 160 || lines <= kMaxPhiLines160);
+           l * lines <= 256 && l * lines >= 16;
 }
 
 // ---------------------------------------------------------------------------
@@ -168,12 +161,12 @@ static hipError_t theta_go(int cols, const double *in, double *out, const ThetaI
                            int n_items, int n_theta, int n_phi, const Twiddle *tw,
                            const double *eneg, const HybridArgs &h, hipStream_t s)
 {
-    constexpr int C = theta_lines<N>();
+    constexpr int C = lines_per_256<N>();
     const int cp_log2 = ilog2_int(cols);
     const int per_group = C / cols;
     const int tiles = (n_phi / 2) / (2 * cols);
     const int groups = (n_items + per_group - 1) / per_group;
-    const dim3 grid((unsigned)(groups * tiles)), block(C * Split<N>::N2);
+    const dim3 grid((unsigned)(groups * tiles)), block(256);
     // the hybrid-capable variant only when the plan has hybrid fields: its
     // detector and two-kind mask cost registers the plain filter does not need
     if (h.present)
@@ -211,8 +204,7 @@ static hipError_t phi_go(const double *in, double *out, const PhiItem *items, in
                          int n_theta, const Twiddle *tw, const double *eneg, const HybridArgs &h,
                          hipStream_t s)
 {
-    if constexpr (LINES * Split<N>::N2 > 256 || LINES * Split<N>::N2 < 16 ||
-                  (N == 160 && LINES > kMaxPhiLines160)) {
+    if constexpr (LINES * Split<N>::N2 > 256 || LINES * Split<N>::N2 < 16) {
         return hipErrorInvalidValue;
     } else {
         const dim3 grid((unsigned)((n_items + LINES - 1) / LINES)), block(LINES * Split<N>::N2);

@@ -75,17 +75,21 @@ __device__ __forceinline__ void st_stream(double *p, double v)
 //     a table of e^{-k}, instead of one exp per mode.
 //   sharp: the same with the factor above the cutoff set to 0.
 //   Gaussian (eq. gaussian_filter): f = exp(log(0.9) (|q| / (c + 1))^2).
-template <int N1, int N2>
-__device__ __forceinline__ void apply_mask(cplx (&v)[N1], int t, int kind, double c,
+template <int N1, int N2, int NV>
+__device__ __forceinline__ void apply_mask(cplx (&v)[NV], int t, int kind, double c,
                                            const double *etab)
 {
     constexpr int N = N1 * N2;
-    constexpr int R = N1 / N2;
+    constexpr int R = NV / N2;
+    constexpr bool PAD = NV != N1;        // padded second stage: rows k1 >= N1 are empty
     constexpr double inv_n = 1.0 / N;
     if (kind == 1) {
         const double inv = 1.0 / (c + 1.0);
         static_for<0, R>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
+            if constexpr (PAD) {
+                if (t + N2 * r >= N1) return;
+            }
             static_for<0, N2>([&](auto kk) {
                 constexpr int k2 = decltype(kk)::value;
                 const int q = t + N2 * r + N1 * k2;
@@ -100,6 +104,9 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[N1], int t, int kind, doubl
         const double g = (kind == 0 ? exp((c - (double)m) - 1.0) : 0.0) * inv_n;
         static_for<0, R>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
+            if constexpr (PAD) {
+                if (t + N2 * r >= N1) return;
+            }
             static_for<0, N2>([&](auto kk) {
                 constexpr int k2 = decltype(kk)::value;
                 const int q = t + N2 * r + N1 * k2;
@@ -122,18 +129,22 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[N1], int t, int kind, doubl
 // order), so one barrier serves both parts and each mode's factors are used
 // as soon as they are formed.  Lines with ka == kb get plain f Z.  All lanes
 // of the workgroup call this together.
-template <int N1, int N2>
-__device__ __forceinline__ void apply_mask_pair(cplx (&v)[N1], int t, int ka, int kb, double c,
+template <int N1, int N2, int NV>
+__device__ __forceinline__ void apply_mask_pair(cplx (&v)[NV], int t, int ka, int kb, double c,
                                                 const double *etab, double *P)
 {
     constexpr int N = N1 * N2;
-    constexpr int R = N1 / N2;
+    constexpr int R = NV / N2;
+    constexpr bool PAD = NV != N1;
     constexpr double inv_n = 1.0 / N;
     const int m = c >= (double)N ? N : (int)floor(c);
     const double g_exp = exp((c - (double)m) - 1.0) * inv_n;
     const double inv_c1 = 1.0 / (c + 1.0);
     static_for<0, R>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
+        if constexpr (PAD) {
+            if (t + N2 * r >= N1) return;
+        }
         static_for<0, N2>([&](auto kk) {
             constexpr int k2 = decltype(kk)::value;
             const int q = t + N2 * r + N1 * k2;
@@ -144,6 +155,9 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[N1], int t, int ka, in
     __syncthreads();
     static_for<0, R>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
+        if constexpr (PAD) {
+            if (t + N2 * r >= N1) return;
+        }
         static_for<0, N2>([&](auto kk) {
             constexpr int k2 = decltype(kk)::value;
             const int q = t + N2 * r + N1 * k2;
@@ -178,11 +192,14 @@ constexpr int line_stride()
 
 // Forward transpose: lane t holds Y[k1][t] in v[k1]; afterwards it holds
 // Y[t + N2 r][n2] in v[r * N2 + n2].  Real and imaginary parts go through LDS
-// in two rounds to halve the LDS footprint.
-template <int N1, int N2>
-__device__ __forceinline__ void transpose_fwd(cplx (&v)[N1], int t, double *L)
+// in two rounds to halve the LDS footprint.  With a padded second stage
+// (NV > N1: N2 does not divide N1) the rows t + N2 r >= N1 do not exist and
+// are set to zero.
+template <int N1, int N2, int NV>
+__device__ __forceinline__ void transpose_fwd(cplx (&v)[NV], int t, double *L)
 {
     constexpr int S = N2 + 1;
+    constexpr bool PAD = NV != N1;
     static_for<0, 2>([&](auto part) {
         constexpr bool im = decltype(part)::value == 1;
         static_for<0, N1>([&](auto kk) {
@@ -190,11 +207,12 @@ __device__ __forceinline__ void transpose_fwd(cplx (&v)[N1], int t, double *L)
             L[k1 * S + t] = im ? v[k1].im : v[k1].re;
         });
         __syncthreads();
-        static_for<0, N1 / N2>([&](auto rr) {
+        static_for<0, NV / N2>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
+            const bool row = !PAD || t + N2 * r < N1;
             static_for<0, N2>([&](auto nn) {
                 constexpr int n2 = decltype(nn)::value;
-                const double x = L[(t + N2 * r) * S + n2];
+                const double x = row ? L[(t + N2 * r) * S + n2] : 0.0;
                 if constexpr (im) v[r * N2 + n2].im = x; else v[r * N2 + n2].re = x;
             });
         });
@@ -202,15 +220,19 @@ __device__ __forceinline__ void transpose_fwd(cplx (&v)[N1], int t, double *L)
     });
 }
 
-// Inverse of transpose_fwd.
-template <int N1, int N2>
-__device__ __forceinline__ void transpose_bwd(cplx (&v)[N1], int t, double *L)
+// Inverse of transpose_fwd (padded rows are dropped).
+template <int N1, int N2, int NV>
+__device__ __forceinline__ void transpose_bwd(cplx (&v)[NV], int t, double *L)
 {
     constexpr int S = N2 + 1;
+    constexpr bool PAD = NV != N1;
     static_for<0, 2>([&](auto part) {
         constexpr bool im = decltype(part)::value == 1;
-        static_for<0, N1 / N2>([&](auto rr) {
+        static_for<0, NV / N2>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
+            if constexpr (PAD) {
+                if (t + N2 * r >= N1) return;
+            }
             static_for<0, N2>([&](auto nn) {
                 constexpr int n2 = decltype(nn)::value;
                 L[(t + N2 * r) * S + n2] = im ? v[r * N2 + n2].im : v[r * N2 + n2].re;
@@ -261,13 +283,16 @@ __device__ __forceinline__ void twiddle_powers(cplx (&v)[NV], const Twiddle *__r
 // holds x[N2 n1 + t] in v[n1]); on return v holds the filtered values at the
 // same positions.  Every lane of the workgroup calls this together.
 // etab: e^{-k}, k <= N/2, in LDS, written before the first barrier here.
-template <int N1, int N2, bool HYB>
-__device__ __forceinline__ void filter_line(cplx (&v)[N1], int t, int kind, int kind_b, bool mixed,
+template <int N1, int N2, bool HYB, int NV>
+__device__ __forceinline__ void filter_line(cplx (&v)[NV], int t, int kind, int kind_b, bool mixed,
                                             double c, double *L, const Twiddle *__restrict__ tw,
                                             const double *etab)
 {
-    constexpr int R = N1 / N2;
-    static_assert(N1 % N2 == 0, "lane count must divide the register count");
+    // R second-stage rows per lane; when N2 does not divide N1 the last row
+    // is padded (NV = R N2 > N1) and its entries k1 >= N1 are skipped
+    constexpr int R = NV / N2;
+    constexpr bool PAD = NV != N1;
+    static_assert(NV % N2 == 0 && NV >= N1 && NV - N1 < N2, "second stage: ceil(N1 / N2) rows");
 
     // forward: N1-point DFTs over n1, twiddle W_N^{t k1}
     dft_reg<N1, false>(v);
@@ -293,7 +318,9 @@ __device__ __forceinline__ void filter_line(cplx (&v)[N1], int t, int kind, int 
     static_for<0, R>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
         dft_reg<N2, true, r * N2>(v);
-        twiddle_powers<N2, true, r * N2>(v, tw, t + N2 * r);
+        // a padded row's twiddles stay inside the table (its result is dropped)
+        const int k1 = t + N2 * r;
+        twiddle_powers<N2, true, r * N2>(v, tw, PAD && k1 >= N1 ? 0 : k1);
     });
     transpose_bwd<N1, N2>(v, t, L);
     dft_reg<N1, true>(v);
@@ -307,20 +334,26 @@ __device__ __forceinline__ void stage_exp_table(double *etab, const double *__re
     for (int i = lane; i <= N / 2; i += (int)blockDim.x) etab[i] = eneg[i];
 }
 
-// N = N1 * N2: N2 lanes per line, N1 values per lane; N2 divides N1 (the
-// transpose gives each lane N1 / N2 whole second-stage transforms).  The
-// lengths 48, 96 and 192 take a radix-3 stage in the N1-point transform, 80
-// and 160 a radix-5 stage.
+// N = N1 * N2: N2 lanes per line, N1 values per lane.  After the transpose
+// each lane holds ceil(N1 / N2) rows of N2 second-stage values: NV values per
+// lane in all (NV = N1 when N2 divides N1; at 160 = 20 x 8 the third row is
+// padded, NV = 24).  The lengths 48, 96 and 192 take a radix-3 stage in the
+// N1-point transform, 80 and 160 a radix-5 stage.
+template <int A, int B>
+struct SplitOf {
+    static constexpr int N1 = A, N2 = B;
+    static constexpr int NV = (A + B - 1) / B * B;
+};
 template <int N> struct Split;
-template <> struct Split<32>  { static constexpr int N1 = 8,  N2 = 4; };
-template <> struct Split<48>  { static constexpr int N1 = 12, N2 = 4; };
-template <> struct Split<64>  { static constexpr int N1 = 8,  N2 = 8; };
-template <> struct Split<80>  { static constexpr int N1 = 20, N2 = 4; };
-template <> struct Split<96>  { static constexpr int N1 = 24, N2 = 4; };
-template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
-template <> struct Split<160> { static constexpr int N1 = 40, N2 = 4; };
-template <> struct Split<192> { static constexpr int N1 = 24, N2 = 8; };
-template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
+template <> struct Split<32>  : SplitOf<8, 4> {};
+template <> struct Split<48>  : SplitOf<12, 4> {};
+template <> struct Split<64>  : SplitOf<8, 8> {};
+template <> struct Split<80>  : SplitOf<20, 4> {};
+template <> struct Split<96>  : SplitOf<24, 4> {};
+template <> struct Split<128> : SplitOf<16, 8> {};
+template <> struct Split<160> : SplitOf<20, 8> {};
+template <> struct Split<192> : SplitOf<24, 8> {};
+template <> struct Split<256> : SplitOf<16, 16> {};
 
 
 // Jameson's detector sigma_i = |u_{i-1} - 2u_i + u_{i+1}| /
@@ -331,8 +364,8 @@ template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
 // hybrid-capable kernels' line stride) and combine their findings in *flag
 // (this line's LDS word).  All lanes call this together; `check` says whether
 // this lane's line needs the detector at all.
-template <int N1, int N2>
-__device__ __forceinline__ int detect_shocks(const cplx (&v)[N1], int t, double *L, int *flag,
+template <int N1, int N2, int NV>
+__device__ __forceinline__ int detect_shocks(const cplx (&v)[NV], int t, double *L, int *flag,
                                              bool check, double eps, double threshold)
 {
     constexpr int N = N1 * N2;
@@ -367,8 +400,8 @@ __device__ __forceinline__ int detect_shocks(const cplx (&v)[N1], int t, double 
 // The two kinds of a packed line: a hybrid line takes the Gaussian where its
 // detector fired (or its recorded decision says so), else the exponential.
 // dec_a / dec_b: byte offsets of the two real lines in h.dec.
-template <int N1, int N2>
-__device__ __forceinline__ void hybrid_kinds(const cplx (&v)[N1], int t, double *L, int *flag,
+template <int N1, int N2, int NV>
+__device__ __forceinline__ void hybrid_kinds(const cplx (&v)[NV], int t, double *L, int *flag,
                                              bool active, int kind, size_t dec_a, size_t dec_b,
                                              const HybridArgs &h, int *ka, int *kb, bool *mixed)
 {
@@ -397,11 +430,6 @@ __device__ __forceinline__ void hybrid_kinds(const cplx (&v)[N1], int t, double 
 // Lanes per line and lines per 256-lane workgroup for each supported N.
 template <int N>
 constexpr int lines_per_256() { return 256 / Split<N>::N2; }
-// Lines per workgroup of the per-plan theta kernel: 256 lanes, except at
-// N = 160, where 64 lines' hybrid spectra (2N + 1 doubles each) would not fit
-// in LDS: 32 lines on 128 lanes.
-template <int N>
-constexpr int theta_lines() { return N == 160 ? 32 : lines_per_256<N>(); }
 
 // ---------------------------------------------------------------------------
 // theta-pass worker.  C complex lines per workgroup (C * N2 lanes, lane
@@ -423,7 +451,7 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
                                             double *etab, int *flags, const HybridArgs &h, int lane)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-    static_assert(C * N2 <= 256 && 256 % (C * N2) == 0, "theta workgroups have 128 or 256 lanes");
+    static_assert(C * N2 == 256, "theta workgroups have 256 lanes");
     const int p = lane % C, t = lane / C;
     const int u = p >> cp_log2, pp = p & ((1 << cp_log2) - 1);
     const bool valid = u < n_valid;
@@ -443,7 +471,7 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
     const int off_n = t * n_phi;
     const int off_s = (N2 - 1 - t) * n_phi + half;
 
-    cplx v[N1];
+    cplx v[Split<N>::NV];
     static_for<0, N1>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
         if (!valid) {
@@ -520,7 +548,7 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
     const int j = it.ring % n_theta;
     const size_t a = (size_t)it.ring * N;
     const size_t b = a + (size_t)(n_theta - 1 - 2 * j) * N;
-    cplx v[N1];
+    cplx v[Split<N>::NV];
     static_for<0, N1>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
         constexpr bool cached = ring_loads_cached<N>();

@@ -233,9 +233,7 @@ def test_batch_create_rejects_bad_patch(L, bad):
 
 def test_batch_create_unsupported_and_empty(L):
     assert _batch_create(L, [dict(), dict(n_theta=12)]) == L.EUNSUPPORTED
-    # lines of 80 and 160 are plan-only
-    assert _batch_create(L, [dict(), dict(n_phi=160)]) == L.EUNSUPPORTED
-    assert _batch_create(L, [dict(n_theta=40, n_phi=64), dict()]) == L.EUNSUPPORTED
+    assert _batch_create(L, [dict(), dict(n_phi=120)]) == L.EUNSUPPORTED
     h = ctypes.c_void_p()
     assert L.load().sphfilt_batch_create(ctypes.byref(h), 0, None, None) == L.EINVAL
 

@@ -1,7 +1,7 @@
 """Seeded sweep over batches of random patches, against the oracle.
 
 Each case draws one to eight patches (theta-line and ring lengths among the
-supported ones, radix-3 lengths included, so patches with fused shells, with
+supported ones, radix-3 and radix-5 lengths included, so patches with fused shells, with
 theta-idle shells and plain ones mix in one work list), per-field kinds including hybrid, parities,
 cut-off scales over two decades, radius tables and floors; a schedule (one
 kernel with per-shell dependencies, two kernels, or two kernels with a
@@ -19,7 +19,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
-LINES = (32, 48, 64, 96, 128, 192, 256)
+LINES = (32, 48, 64, 80, 96, 128, 160, 192, 256)
 
 
 @pytest.fixture(scope="module")
