@@ -239,3 +239,36 @@ def test_radix3_grid_schedules_and_hybrid(torch_gpu, n_theta, n_phi):
         same_cols = [z for c, l, z in outs if c == cols]
         assert all(bitwise(y, z) for z in same_cols), (cols, lines)
     plan.close()
+
+
+@pytest.mark.parametrize("grid", ["fft96_bh", "explosion"])
+def test_mixed_radix_full_size_sampled_shells(torch_gpu, grid):
+    """The mixed-radix benchmark grids at full size, in the launch shape the
+    benchmark times (in place, default schedule): 24 x 128 x 96 x 192 at
+    cal-L = 2 and 24 x 160 x 80 x 160 at cal-L = 4, and both dense.  The
+    oracle checks sampled whole shells, theta-filtered and theta-idle ones."""
+    torch = torch_gpu
+    shape, L_paper = {"fft96_bh": ((24, 128, 96, 192), 2.0), "explosion": ((24, 160, 80, 160), 4.0)}[grid]
+    F, R, T, P = shape
+    rng = np.random.default_rng(P)
+    x = rng.standard_normal(shape)
+    parity = np.where(np.arange(F) % 3 == 2, -1, 1).astype(np.int32)
+    print(f"[gpu] mixed-radix {grid} {shape}", flush=True)
+    for L, rho in ((L_paper, None), (0.2, np.ones(R))):
+        plan = make_plan(shape, parity, np.full(F, L), rho)
+        xd = torch.from_numpy(x).cuda()
+        plan.apply(xd, out=xd)
+        ya = torch.from_numpy(x).cuda()
+        plan.apply_adjoint(ya, out=ya)
+        torch.cuda.synchronize()
+        fwd, adj = xd.cpu().numpy(), ya.cpu().numpy()
+        del xd, ya
+        rho_all = np.arange(R) + 0.5 if rho is None else rho
+        picks = [(0, 0), (F - 1, R - 1), (2, 5), (7, R // 2)] + \
+            [tuple(v) for v in zip(rng.integers(0, F, 3), rng.integers(0, R, 3))]
+        for f, i in picks:
+            sub = x[f:f + 1, i:i + 1]
+            kw = dict(parity=parity[f:f + 1], rho=rho_all[i:i + 1], L=L)
+            assert rel(fwd[f:f + 1, i:i + 1], oracle.forward(sub, **kw)) <= TOL, (grid, L, f, i)
+            assert rel(adj[f:f + 1, i:i + 1], oracle.adjoint(sub, **kw)) <= TOL, (grid, L, f, i)
+        plan.close()
