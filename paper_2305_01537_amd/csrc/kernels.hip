@@ -24,7 +24,8 @@ template <int N, int LINES, bool HYB>
 constexpr int pass_waves()
 {
     constexpr int bytes = 8 * LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
-    return (HYB || Split<N>::NV == 24 && Split<N>::N2 == 8) && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
+    constexpr bool wide = N == 160 || N == 192;
+    return (HYB || wide) && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
 }
 
 // theta-pass: workgroup b handles shell group g = b / tiles (S = C / cp shells
