@@ -55,11 +55,12 @@ static_assert(batch_lds_fits<32, false>() && batch_lds_fits<64, false>() &&
                   batch_lds_fits<96, true>() && batch_lds_fits<160, true>() &&
                   batch_lds_fits<192, true>(),
               "batch LDS holds every worker's line scratch");
-// Waves per SIMD the instances ask for.  The R3 instances take one: their
-// 24 values per lane need more than 256 registers, and the hybrid one's LDS
-// (a whole spectrum per line of 96 or 192) fits one workgroup per CU.
+// Waves per SIMD the instances ask for.  The hybrid R3 instances take one:
+// their LDS (a whole spectrum per line of 96 or 192) fits one workgroup per
+// CU.  The plain one-shot R3 instance asks for two (its 24 values per lane
+// need a little over 256 registers; two waves with a small spill beat one).
 template <bool HYB, bool R3>
-constexpr int oneshot_waves() { return R3 ? 1 : (HYB ? 2 : 1); }
+constexpr int oneshot_waves() { return R3 ? (HYB ? 1 : 2) : (HYB ? 2 : 1); }
 template <bool HYB, bool R3>
 constexpr int persistent_waves() { return R3 ? 1 : (HYB ? 1 : 2); }
 
