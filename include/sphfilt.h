@@ -209,7 +209,7 @@ int sphfilt_plan_set_schedule(sphfilt_plan plan, int theta_cols, int phi_lines);
 int sphfilt_plan_get_schedule(sphfilt_plan plan, int *theta_cols, int *phi_lines);
 
 /*
- * Fused shells.  On grids with n_phi = 2 * n_theta and n_phi <= 128 a whole
+ * Fused shells.  On grids with n_phi = 2 * n_theta in {32, 64, 128} a whole
  * shell (field, radius) fits in one workgroup's LDS.  A shell whose every
  * theta line and every ring is filtered (no identity line) then goes through
  * one kernel that loads it once, runs both passes in LDS and registers, and

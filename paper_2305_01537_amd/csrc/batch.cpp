@@ -237,7 +237,7 @@ void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
 // kernel's second instance.
 bool mixed_radix_line(int n) { return (n & (n - 1)) != 0; }
 
-// A patch whose theta-filtered shells are all fused (n_phi = 2 n_theta <= 128,
+// A patch whose theta-filtered shells are all fused (n_phi = 2 n_theta in {32, 64, 128},
 // see build_items) runs entirely in the first pass: groups of whole shells
 // (both passes, add_fused_shells), and the ring pairs of its theta-idle shells
 // (add_rest_rings; out of place also their identity rings, copied).  Nothing

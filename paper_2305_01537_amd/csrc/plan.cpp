@@ -10,7 +10,7 @@
 // sharp filters) are sorted after the others: an in-place call launches over
 // the non-identity prefix only, an out-of-place call over all items and the
 // identity ones are copied.
-// On grids whose shells fit in LDS (n_phi = 2 n_theta <= 128), shells with no
+// On grids whose shells fit in LDS (n_phi = 2 n_theta in {32, 64, 128}), shells with no
 // identity line are run by the fused shell kernel (both passes, one HBM round
 // trip), in one launch with the ring pairs of the remaining shells.
 #include "../../include/sphfilt.h"

@@ -72,7 +72,7 @@ hipError_t launch_shell_phi(bool adjoint, int n_theta, int n_phi, const double *
                             const PhiItem *rings, int n_rings, const Twiddle *tw,
                             const double *eneg, const HybridArgs &ht, const HybridArgs &hp,
                             hipStream_t stream);
-// n_phi = 2 n_theta and a shell fits in one workgroup's LDS (n_phi <= 128).
+// n_phi = 2 n_theta in {32, 64, 128}: whole shells per 256-lane workgroup.
 bool shell_fusable(int n_theta, int n_phi);
 int shells_per_group(int n_phi);
 

@@ -211,7 +211,7 @@ class Plan:
         return a.value, b.value
 
     def set_fused(self, enable: bool):
-        """Fuse the shells the grid allows (n_phi = 2 n_theta <= 128) or always
+        """Fuse the shells the grid allows (n_phi = 2 n_theta in {32, 64, 128}) or always
         run two passes; see sphfilt_plan_set_fused."""
         _lib.check("sphfilt_plan_set_fused", self._lib.sphfilt_plan_set_fused(self._h, int(bool(enable))))
 
