@@ -179,13 +179,14 @@ def calibrate_copy(torch, x, reps=3):
     return {"copy_bytes_each": 2 * x.numel() * 8, "reps": reps}
 
 
-def bench_patches(torch, steps, stream):
+def bench_patches(torch, steps, stream, n_theta_choices=(16, 32, 64, 128)):
     """64 uneven patches: one tuned graph-replayed batch launch against one plan
-    (two kernel launches) per patch, forward in place, same buffers."""
+    (two kernel launches) per patch, forward in place, same buffers.
+    n_theta_choices: the patches' n_theta (n_phi = 2 n_theta)."""
     import tempfile
     from paper_2305_01537_amd import synth
     from paper_2305_01537_amd.filter import Batch, Plan
-    pts = synth.patches(with_values=False)
+    pts = synth.patches(with_values=False, n_theta_choices=n_theta_choices)
     g = torch.Generator(device="cuda").manual_seed(4)
     xs = [torch.randn((p.n_fields, p.n_r, p.n_theta, p.n_phi), dtype=torch.float64, device="cuda",
                       generator=g) for p in pts]
@@ -526,6 +527,14 @@ def main():
         log("timing radix-3 and radix-5 lines (96 x 192, 80 x 160)")
         extra["mixed_radix"] = bench_mixed_radix(torch, max(10, args.steps // 2), stream)
         log(f"mixed-radix lines: {extra['mixed_radix']}")
+        for key, choices in (("patches_radix3", (24, 48, 96)), ("patches_radix5", (40, 80))):
+            log(f"timing 64 patches with n_theta in {choices}")
+            r = bench_patches(torch, max(10, args.steps // 2), stream, choices)
+            extra[key] = {k: r[k] for k in ("points", "algorithmic_bytes", "batched_forward_ms",
+                                            "per_patch_launch_ms", "batched_GBps",
+                                            "batched_over_per_patch_speedup", "schedule")}
+            extra[key]["n_theta_choices"] = list(choices)
+            log(f"{key}: {extra[key]}")
 
     cpu = None
     if not args.no_cpu_baseline:
