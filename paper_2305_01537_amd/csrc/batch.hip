@@ -55,14 +55,14 @@ static_assert(batch_lds_fits<32, false>() && batch_lds_fits<64, false>() &&
                   batch_lds_fits<96, true>() && batch_lds_fits<160, true>() &&
                   batch_lds_fits<192, true>(),
               "batch LDS holds every worker's line scratch");
-// Waves per SIMD the instances ask for.  The hybrid R3 instances take one:
-// their LDS (a whole spectrum per line of 96 or 192) fits one workgroup per
-// CU.  The plain one-shot R3 instance asks for two (its 24 values per lane
-// need a little over 256 registers; two waves with a small spill beat one).
+// Waves per SIMD the instances ask for.  One-shot: two for the hybrid forms
+// and for the plain R3 form (each needs a little over 256 registers; two
+// waves with a small spill beat one).  Persistent: two for the plain
+// power-of-two form, one for the others.
 template <bool HYB, bool R3>
-constexpr int oneshot_waves() { return R3 ? (HYB ? 1 : 2) : (HYB ? 2 : 1); }
+constexpr int oneshot_waves() { return HYB || R3 ? 2 : 1; }
 template <bool HYB, bool R3>
-constexpr int persistent_waves() { return R3 ? 1 : (HYB ? 1 : 2); }
+constexpr int persistent_waves() { return HYB || R3 ? 1 : 2; }
 
 // Hybrid lines in a batch decide from their data; decisions are not recorded.
 __device__ __forceinline__ HybridArgs batch_hybrid(const BatchPatchDev &pd)

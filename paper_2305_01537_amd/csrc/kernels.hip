@@ -15,17 +15,13 @@ namespace sphfilt {
 
 // Waves per SIMD a pass kernel asks the compiler for (it caps the registers
 // per lane at 512 / waves).  The hybrid-capable instances: two, where two
-// workgroups' line scratch (a whole spectrum per line) fits in LDS, else one
-// (lines of 96, 160 and 192 at 256 lanes).  The plain instances with 24
-// values per lane (N = 160, 192): two as well, for a small spill; they would
-// otherwise take a little over 256 registers and run one wave.  The other
-// plain instances: no target (they fit two or more waves by themselves).
+// workgroups' line scratch (a whole spectrum per line) fits in LDS, else one.
+// The plain instances: no target (they fit two or more waves by themselves).
 template <int N, int LINES, bool HYB>
 constexpr int pass_waves()
 {
     constexpr int bytes = 8 * LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
-    constexpr bool wide = N == 160 || N == 192;
-    return (HYB || wide) && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
+    return HYB && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
 }
 
 // theta-pass: workgroup b handles shell group g = b / tiles (S = C / cp shells

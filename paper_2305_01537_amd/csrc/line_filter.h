@@ -336,9 +336,13 @@ __device__ __forceinline__ void stage_exp_table(double *etab, const double *__re
 
 // N = N1 * N2: N2 lanes per line, N1 values per lane.  After the transpose
 // each lane holds ceil(N1 / N2) rows of N2 second-stage values: NV values per
-// lane in all (NV = N1 when N2 divides N1; at 160 = 20 x 8 the third row is
-// padded, NV = 24).  The lengths 48, 96 and 192 take a radix-3 stage in the
-// N1-point transform, 80 and 160 a radix-5 stage.
+// lane in all (NV = N1 when N2 divides N1, else the last row is padded: 96 =
+// 12 x 8 and 80 = 10 x 8 hold 16, 192 = 12 x 16 and 160 = 10 x 16 hold 16 with
+// one row per lane, 4 or 6 of the 16 lanes' rows padded).  The lengths 48,
+// 96 and 192 take a radix-3 stage in the N1-point transform, 80 and 160 a
+// radix-5 stage.  Splits with more lanes per line were chosen over ones with
+// fewer padded values (24 x 4, 24 x 8, 20 x 4, 20 x 8): wider row pieces per
+// load and fewer registers.
 template <int A, int B>
 struct SplitOf {
     static constexpr int N1 = A, N2 = B;
@@ -348,11 +352,11 @@ template <int N> struct Split;
 template <> struct Split<32>  : SplitOf<8, 4> {};
 template <> struct Split<48>  : SplitOf<12, 4> {};
 template <> struct Split<64>  : SplitOf<8, 8> {};
-template <> struct Split<80>  : SplitOf<20, 4> {};
-template <> struct Split<96>  : SplitOf<24, 4> {};
+template <> struct Split<80>  : SplitOf<10, 8> {};
+template <> struct Split<96>  : SplitOf<12, 8> {};
 template <> struct Split<128> : SplitOf<16, 8> {};
-template <> struct Split<160> : SplitOf<20, 8> {};
-template <> struct Split<192> : SplitOf<24, 8> {};
+template <> struct Split<160> : SplitOf<10, 16> {};
+template <> struct Split<192> : SplitOf<12, 16> {};
 template <> struct Split<256> : SplitOf<16, 16> {};
 
 

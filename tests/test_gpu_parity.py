@@ -226,7 +226,7 @@ def test_radix3_grid_schedules_and_hybrid(torch_gpu, n_theta, n_phi):
             plan.set_schedule(theta_cols=cols)
         except SphfiltError:
             continue
-        for lines in (4, 16, 64):
+        for lines in (4, 16, 32, 64):
             try:
                 plan.set_schedule(phi_lines=lines)
             except SphfiltError:
@@ -234,7 +234,7 @@ def test_radix3_grid_schedules_and_hybrid(torch_gpu, n_theta, n_phi):
             y = gpu_call(torch, plan, "forward", x, inplace=False)
             assert rel(y, ref) <= TOL, (cols, lines, rel(y, ref))
             outs.append((cols, lines, y))
-    assert len(outs) >= 3
+    assert len(outs) >= 3     # at least two phi launch shapes for some theta tile
     for cols, lines, y in outs:
         same_cols = [z for c, l, z in outs if c == cols]
         assert all(bitwise(y, z) for z in same_cols), (cols, lines)
