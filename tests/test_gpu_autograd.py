@@ -112,3 +112,30 @@ def test_gradient_finite_differences_and_checkpointing(env):
           flush=True)
     assert np.median(rel_errs) <= 1e-7
     assert excess <= 1.0
+
+
+@pytest.mark.parametrize("shape", [(4, 10, 48, 96), (3, 8, 80, 160), (2, 6, 96, 192)])
+def test_dot_product_and_gradient_on_mixed_radix_grids(env, shape):
+    """Lines with a radix-3 or radix-5 stage: the adjoint call is the transpose
+    of the forward one (dot test), and autograd's gradient through the filter
+    is that adjoint, bit for bit."""
+    torch = env[0]
+    from paper_2305_01537_amd.autograd import sph_filter
+    from paper_2305_01537_amd.filter import Plan
+    F, R, T, P = shape
+    rng = np.random.default_rng(T + P)
+    parity = np.where(np.arange(F) % 2 == 0, 1, -1).astype(np.int32)
+    kind = np.array([0, 1, 2, 0][:F], dtype=np.int32)
+    plan = Plan(R, T, P, F, parity=parity, L=0.5, kind=kind)
+    x = rng.standard_normal(shape)
+    y = rng.standard_normal(shape)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    Fx = plan.apply(xd).cpu().numpy()
+    Fty = plan.apply_adjoint(yd).cpu().numpy()
+    err = float(abs(_dot(Fx, y) - _dot(x, Fty)) / (np.linalg.norm(Fx) * np.linalg.norm(y)))
+    print(f"[gpu] dot test {shape}: {err:.2e}", flush=True)
+    assert err <= 1e-13
+    xv = xd.clone().requires_grad_(True)
+    sph_filter(xv, plan).backward(yd)
+    assert torch.equal(xv.grad, plan.apply_adjoint(yd))
+    plan.close()
