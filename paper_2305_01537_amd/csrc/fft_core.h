@@ -6,14 +6,16 @@
 //   X[k1 + N1 k2] = sum_n2 W_N2^{n2 k2} W_N^{n2 k1} sum_n1 x[N2 n1 + n2] W_N1^{n1 k1}
 //
 // done as: an N1-point DFT in registers, a twiddle by W_N^{t k1}, one LDS
-// transpose, N1/N2 independent N2-point DFTs in registers; then the mask;
-// then the same steps in reverse (inverse DFTs, conjugate twiddles, one LDS
+// transpose, ceil(N1/N2) rows of N2-point DFTs per lane in registers (the
+// last row partly padding when N2 does not divide N1); then the mask; then
+// the same steps in reverse (inverse DFTs, conjugate twiddles, one LDS
 // transpose) so that every lane ends up with its own N1 input positions again.
 // Two HBM touches per line (load, store) and two LDS transposes in between.
 //
 // The small in-register DFTs are radix-2 decimation in frequency with their
-// twiddles as compile-time constants; the output permutation is a register
-// renaming, so it costs nothing.
+// twiddles as compile-time constants, with one radix-3 or radix-5 stage in
+// front for sizes 3 * 2^k and 5 * 2^k; the output permutations are register
+// renamings, so they cost nothing.
 #pragma once
 #include <hip/hip_runtime.h>
 
