@@ -88,7 +88,7 @@ struct sphfilt_batch_s {
     std::vector<GraphEntry> graphs;
     int split = 0, wpc = -1;           // schedule: see effective_wpc
     int hybrid = 0;                    // some patch has a hybrid field
-    int variant = 0;                   // kernel instance: kBatchHybrid | kBatchRadix3
+    int variant = 0;                   // kernel instance: kBatchHybrid | kBatchMixedRadix
     double tuned_us = -1.0;
     uint64_t clock = 0;
     hipStream_t capture_stream = nullptr;
@@ -658,12 +658,12 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
             b->arch = prop.gcnArchName;
             const size_t colon = b->arch.find(':');
             if (colon != std::string::npos) b->arch.resize(colon);
-            bool r3 = false;
+            bool mixed = false;
             for (int p = 0; p < n_patches; ++p) {
                 b->hybrid |= hybrid_args(&desc[p].cut, desc[p].n_fields).present;
-                r3 = r3 || mixed_radix_line(2 * desc[p].n_theta) || mixed_radix_line(desc[p].n_phi);
+                mixed = mixed || mixed_radix_line(2 * desc[p].n_theta) || mixed_radix_line(desc[p].n_phi);
             }
-            b->variant = (b->hybrid ? kBatchHybrid : 0) | (r3 ? kBatchRadix3 : 0);
+            b->variant = (b->hybrid ? kBatchHybrid : 0) | (mixed ? kBatchMixedRadix : 0);
             b->max_wpc = batch_blocks_per_cu(b->variant);
             b->signature = signature(b->arch, n_patches, desc);
         }

@@ -27,27 +27,27 @@ namespace sphfilt {
 
 // LDS of the largest worker: the staged shells of the fused worker
 // (ShellShape<128>::lds), which also covers the line scratch of every
-// theta/phi group, hybrid spectra included.  The instance that also takes
-// the lengths that are not powers of two (48, 80, 96, 160, 192: R3) needs
-// more for their hybrid spectra.
+// theta/phi group, hybrid spectra included; for the instance that also
+// takes the lengths that are not powers of two (MIXED) it is the larger of
+// that and their line scratch (which fits in it with the current splits).
 template <int N, bool HYB>
 constexpr int batch_line_lds()
 {
     return lines_per_256<N>() * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
 }
-template <bool HYB, bool R3>
+template <bool HYB, bool MIXED>
 constexpr int batch_lds()
 {
     constexpr int a = ShellShape<128>::lds;
     constexpr int b = batch_line_lds<96, HYB>() > batch_line_lds<192, HYB>() ? batch_line_lds<96, HYB>()
                                                                           : batch_line_lds<192, HYB>();
-    return R3 && b > a ? b : a;
+    return MIXED && b > a ? b : a;
 }
-template <int N, bool R3>
+template <int N, bool MIXED>
 constexpr bool batch_lds_fits()
 {
-    return batch_lds<true, R3>() >= batch_line_lds<N, true>() &&
-           batch_lds<false, R3>() >= batch_line_lds<N, false>();
+    return batch_lds<true, MIXED>() >= batch_line_lds<N, true>() &&
+           batch_lds<false, MIXED>() >= batch_line_lds<N, false>();
 }
 static_assert(batch_lds_fits<32, false>() && batch_lds_fits<64, false>() &&
                   batch_lds_fits<128, false>() && batch_lds_fits<256, false>() &&
@@ -56,13 +56,13 @@ static_assert(batch_lds_fits<32, false>() && batch_lds_fits<64, false>() &&
                   batch_lds_fits<192, true>(),
               "batch LDS holds every worker's line scratch");
 // Waves per SIMD the instances ask for.  One-shot: two for the hybrid forms
-// and for the plain R3 form (each needs a little over 256 registers; two
-// waves with a small spill beat one).  Persistent: two for the plain
-// power-of-two form, one for the others.
-template <bool HYB, bool R3>
-constexpr int oneshot_waves() { return HYB || R3 ? 2 : 1; }
-template <bool HYB, bool R3>
-constexpr int persistent_waves() { return HYB || R3 ? 1 : 2; }
+// (a little over 256 registers: two waves with a small spill beat one) and
+// for the plain MIXED form.  Persistent: two for the plain power-of-two
+// form, one for the others.
+template <bool HYB, bool MIXED>
+constexpr int oneshot_waves() { return HYB || MIXED ? 2 : 1; }
+template <bool HYB, bool MIXED>
+constexpr int persistent_waves() { return HYB || MIXED ? 1 : 2; }
 
 // Hybrid lines in a batch decide from their data; decisions are not recorded.
 __device__ __forceinline__ HybridArgs batch_hybrid(const BatchPatchDev &pd)
@@ -127,7 +127,7 @@ struct BatchArgs {
 
 // One work item k (workgroup-uniform): wait for its shells (second pass),
 // filter, signal its shells (first pass).
-template <bool HYB, bool R3>
+template <bool HYB, bool MIXED>
 __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, double *lds,
                                          double *etab, int *flags)
 {
@@ -164,7 +164,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
         case 64: theta_item<64, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
         case 128: theta_item<128, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
         default:
-            if constexpr (R3) {
+            if constexpr (MIXED) {
                 switch (pd.n_line) {
                 case 48: theta_item<48, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
                 case 80: theta_item<80, HYB>(w, pd, src, dst, a.th, a.eneg, lds, etab, flags, lane); break;
@@ -190,7 +190,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
         case 64: phi_item<64, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
         case 128: phi_item<128, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
         default:
-            if constexpr (R3) {
+            if constexpr (MIXED) {
                 switch (pd.n_phi) {
                 case 48: phi_item<48, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
                 case 80: phi_item<80, HYB>(w, pd, src, dst, a.ph, a.eneg, lds, etab, flags, lane); break;
@@ -238,18 +238,18 @@ __device__ __forceinline__ int next_ticket(int *ticket, int *cur)
 // The hybrid form needs a little more than 256 registers: two waves per SIMD
 // with a small spill (128 bytes per lane) beat one wave without (the hybrid
 // 64-patch batch: 2.05 against 2.64 ms).
-// R3: the instance that also takes lines of 48, 80, 96, 160 and 192 points
-// (launched only for batches that have such a patch; their 20-24 values per
-// lane and larger hybrid LDS would otherwise weigh on every batch).
-template <bool HYB, bool R3>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(oneshot_waves<HYB, R3>()))) void batch_kernel_oneshot(BatchArgs a)
+// MIXED: the instance that also takes lines of 48, 80, 96, 160 and 192 points,
+// launched only for batches that have such a patch, so that the power-of-two
+// instance keeps its code and register allocation.
+template <bool HYB, bool MIXED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(oneshot_waves<HYB, MIXED>()))) void batch_kernel_oneshot(BatchArgs a)
 {
-    __shared__ double lds[batch_lds<HYB, R3>()];
+    __shared__ double lds[batch_lds<HYB, MIXED>()];
     __shared__ double etab[129];
     __shared__ int flags[64];
     __shared__ int cur;
     const int k = a.use_deps ? next_ticket(a.ticket, &cur) : (int)blockIdx.x;
-    if (k < a.n_work) run_item<HYB, R3>(a, k, threadIdx.x, lds, etab, flags);
+    if (k < a.n_work) run_item<HYB, MIXED>(a, k, threadIdx.x, lds, etab, flags);
 }
 
 // Persistent form: a fixed grid; each workgroup takes tickets until the list
@@ -258,11 +258,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(oneshot_wav
 // items (it would otherwise not fit in 256 registers).  The hybrid form, with
 // the detector and the mixed-pair mask, needs more than 256 registers; it runs
 // one wave per SIMD (at two it would spill 240 bytes per lane and lose a third).
-template <bool HYB, bool R3>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_waves<HYB, R3>()))) void batch_kernel_persistent(
+template <bool HYB, bool MIXED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_waves<HYB, MIXED>()))) void batch_kernel_persistent(
     BatchArgs a)
 {
-    __shared__ double lds[batch_lds<HYB, R3>()];
+    __shared__ double lds[batch_lds<HYB, MIXED>()];
     __shared__ double etab[129];
     __shared__ int flags[64];
     __shared__ int cur;
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_
         if (k >= a.n_work) break;
         unsigned lane;
         asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((unsigned)threadIdx.x));
-        run_item<HYB, R3>(a, k, (int)lane, lds, etab, flags);
+        run_item<HYB, MIXED>(a, k, (int)lane, lds, etab, flags);
     }
 }
 
@@ -318,7 +318,7 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
         if (one) batch_kernel_oneshot<true, false><<<g, 256, 0, s>>>(a);
         else batch_kernel_persistent<true, false><<<g, 256, 0, s>>>(a);
         break;
-    case kBatchRadix3:
+    case kBatchMixedRadix:
         if (one) batch_kernel_oneshot<false, true><<<g, 256, 0, s>>>(a);
         else batch_kernel_persistent<false, true><<<g, 256, 0, s>>>(a);
         break;
@@ -337,7 +337,7 @@ int batch_blocks_per_cu(int variant)
     switch (variant & 3) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<false, false>, 256, 0); break;
     case kBatchHybrid: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<true, false>, 256, 0); break;
-    case kBatchRadix3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<false, true>, 256, 0); break;
+    case kBatchMixedRadix: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<false, true>, 256, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_persistent<true, true>, 256, 0); break;
     }
     if (e != hipSuccess) return 1;

@@ -49,9 +49,9 @@ hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n
 // grid > 0: persistent form with `grid` workgroups; grid <= 0: one workgroup
 // per item.
 // Kernel instance of a batch: kBatchHybrid when some patch has a hybrid field
-// (the detector and mixed-pair mask), kBatchRadix3 when some patch has lines
+// (the detector and mixed-pair mask), kBatchMixedRadix when some patch has lines
 // that are not powers of two (48, 80, 96, 160 or 192 points).
-constexpr int kBatchHybrid = 1, kBatchRadix3 = 2;
+constexpr int kBatchHybrid = 1, kBatchMixedRadix = 2;
 hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const BatchPatchDev *patches,
                         const double *const *ins, double *const *outs, const ThetaItem *th,
                         const PhiItem *ph, const double *fc, const int *shells, int *counters,
