@@ -122,6 +122,32 @@ def test_identity_cutoff_is_bitwise(torch_gpu):
         assert ok_o and ok_i, call
 
 
+@pytest.mark.parametrize("n_line", [32, 48, 64, 80, 96, 128, 160, 192, 256])
+def test_sharp_cutoff_on_every_mode(torch_gpu, n_line):
+    # The floor sets an exact integer cutoff k on every θ and φ line (L is far
+    # too small to lift it), so the sharp mask meets a mode exactly at q = k and
+    # must keep it.  Grid n_phi = 2 n_theta = n_line: both passes run lines of
+    # this length, and the fused-shell kernel runs where that grid has one.
+    from paper_2305_01537_amd.filter import Plan
+    rng = np.random.default_rng(n_line)
+    shape = (2, 1, n_line // 2, n_line)
+    x = rng.standard_normal(shape)
+    parity = np.array([1, -1], dtype=np.int32)
+    L = np.array([1e-6, 1e-6])
+    kind = np.array([2, 2], dtype=np.int32)
+    print(f"[gpu] sharp integer cutoffs {shape}", flush=True)
+    xd = torch_gpu.from_numpy(x).cuda()
+    for k in range(2, n_line // 2):
+        plan = Plan(1, n_line // 2, n_line, 2, parity=parity, L=L, kind=kind, floor_modes=float(k))
+        st = plan.stats()
+        assert st["theta_shells_active"] == 2 and st["phi_rings_active"] == n_line, (k, st)
+        out = plan.apply(xd)
+        torch_gpu.cuda.synchronize()
+        ref = oracle.forward(x, parity=parity, L=L, kind=kind, floor_modes=float(k))
+        assert rel(out.cpu().numpy(), ref) <= TOL, (n_line, k, rel(out.cpu().numpy(), ref))
+        plan.close()
+
+
 def test_schedules_are_bitwise_equal_and_deterministic(torch_gpu):
     """The phi launch shape never changes the arithmetic of a line, so results are
     bitwise equal across it.  The theta tile width C decides which two meridian

@@ -38,6 +38,7 @@ MUTANTS = {
     "latitude not cell-centred": ("((double)jm + 0.5) * ORC_PI", "((double)jm + 1.0) * ORC_PI"),
     "inverse normalisation": ("out[n] = re / (double)N;", "out[n] = re / (double)(N - 1);"),
     "conjugated forward transform": ("im -= g[n] * st[m];", "im += g[n] * st[m];"),
+    "sharp mask drops the edge mode": ("return qhat <= c ? 1.0 : 0.0;", "return qhat < c ? 1.0 : 0.0;"),
     "gaussian constant": ("exp(log(0.9) * u * u)", "exp(log(0.8) * u * u)"),
     "floor ignored": ("return c > floor_modes ? c : floor_modes;\n}\n\n/* sin", "return c;\n}\n\n/* sin"),
     "phi cutoff without sin(theta)": ("double c = 2.0 * rho * orc_sin_theta(j, n_theta) * L;", "double c = 2.0 * rho * L;"),
@@ -81,6 +82,7 @@ def _pin_cases():
         lambda m: P.test_p8_cutoff_depends_on_r_and_latitude(m),
         lambda m: [P.test_p10_library_fft_matches(m, k) for k in (0, 1, 2)],
         lambda m: P.test_p10_library_fft_matches_radix3_lengths(m, 24, 48),
+        lambda m: P.test_p10_sharp_cutoff_on_a_mode_keeps_it(m),
         lambda m: P.test_hybrid_smooth_fields_take_the_exponential_filter(m),
         lambda m: P.test_hybrid_ring_with_a_jump_takes_the_gaussian(m),
         lambda m: P.test_hybrid_theta_decision_uses_the_extended_line(m),

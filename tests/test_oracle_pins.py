@@ -430,6 +430,24 @@ def test_p10_library_fft_matches(oracle_mod, kind):
         assert rel_err(oracle_mod.adjoint(w.x, parity=w.parity, rho=w.rho, L=L, kind=kind), refa) <= 1e-13
 
 
+def test_p10_sharp_cutoff_on_a_mode_keeps_it(oracle_mod):
+    # rho = 1/2 makes l_max = L exactly, so an integer L puts the sharp mask's
+    # edge on a mode: that mode stays (f = 1 for qhat <= c).  The phi cutoff is
+    # held at the floor of 2 modes by a tiny L, the same edge on the rings.
+    rng = np.random.default_rng(5)
+    T, P = 24, 48
+    x = rng.standard_normal((2, 1, T, P))
+    par, rho = np.array([1, -1]), np.array([0.5])
+    kinds = np.full(2, SHARP)
+    for k in (2, 3, 7, 12, 23):
+        Lv = np.full(2, float(k))
+        ref = fft_theta_pass(x, par, rho, Lv, kinds)
+        assert rel_err(oracle_mod.theta_pass(x, parity=par, rho=rho, L=Lv, kind=SHARP), ref) <= 1e-13, k
+    Lv = np.full(2, 1e-6)
+    ref = fft_phi_pass(x, par, rho, Lv, kinds)
+    assert rel_err(oracle_mod.phi_pass(x, parity=par, rho=rho, L=Lv, kind=SHARP), ref) <= 1e-13
+
+
 @pytest.mark.parametrize("T,P", [(96, 192), (48, 96), (24, 48), (80, 160), (40, 80)])
 def test_p10_library_fft_matches_radix3_lengths(oracle_mod, T, P):
     # lines of 3 * 2^k and 5 * 2^k points: numpy's FFT against the oracle's
