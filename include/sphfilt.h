@@ -145,9 +145,12 @@ int sphfilt_plan_destroy(sphfilt_plan plan);
 /*
  * out = Phi(Theta(in)): the double FFT filter, theta first (Sec. II.B).
  *   in, out  device pointers to n_fields*n_r*n_theta*n_phi doubles, layout
- *            [f][r][theta][phi].  in == out (in place) is allowed and is the
- *            fast path: lines whose mask is all ones are not touched.  Any
- *            other overlap of the two ranges is SPHFILT_EINVAL.
+ *            [f][r][theta][phi], each 16-byte aligned (hipMalloc and the
+ *            PyTorch allocator give 256-byte alignment; the theta pass moves
+ *            two adjacent doubles per access), else SPHFILT_EINVAL.  in == out
+ *            (in place) is allowed and is the fast path: lines whose mask is
+ *            all ones are not touched.  Any other overlap of the two ranges is
+ *            SPHFILT_EINVAL.
  *   stream   a hipStream_t (NULL = the null stream).
  * Enqueues two kernels and returns; SPHFILT_EDEVICE if a launch fails.
  */
@@ -190,16 +193,18 @@ int sphfilt_workload_stats(int n_r, int n_theta, int n_phi, int n_fields, const 
                            const sphfilt_cutoff *cut, sphfilt_stats *out);
 
 /*
- * Launch shape of a plan's kernels (tuning; results are bitwise independent
- * of phi_lines, and theta_cols only moves round-off, see below).
- *   theta_cols  meridian pairs per half sub-tile of the theta kernel: 4, 8,
- *               16, 32 or 64, at most n_phi/4, at most the lines of one
- *               theta workgroup (16 for 2*n_theta = 256, 32 for 64, 128,
- *               160 or 192, 64 for 32, 48, 80 or 96), and 2*theta_cols must
- *               divide n_phi/2.  The default is the widest such tile.  A
- *               256-lane workgroup covers 256/lanes/theta_cols shells; two
- *               meridian pairs theta_cols apart share one complex transform,
- *               so changing it changes round-off only.  0 keeps the value.
+ * Launch shape of a plan's kernels (tuning only: results are bitwise
+ * independent of phi_lines, and of theta_cols except where 2*n_theta = 256,
+ * where it moves round-off only; see below).
+ *   theta_cols  complex lines per shell in one theta workgroup: 4, 8, 16,
+ *               32 or 64, at most n_phi/4, at most the lines of one theta
+ *               workgroup (16 for 2*n_theta = 160, 192 or 256, 32 for 64,
+ *               80, 96 or 128, 64 for 32 or 48), and 2*theta_cols must
+ *               divide n_phi/2.  A workgroup covers 2*theta_cols meridian
+ *               pairs of each of its 256/lanes/theta_cols shells; each line
+ *               packs two adjacent ones, or, where 2*n_theta = 256, two
+ *               theta_cols apart.  The default is the widest such tile.
+ *               0 keeps the value.
  *   phi_lines   ring pairs per workgroup of the phi kernel: 4, 8, 16, 32 or
  *               64 (at most 256 lanes per workgroup).  0 keeps the value.
  * Returns SPHFILT_EINVAL for other values.  Not thread-safe against
@@ -299,7 +304,8 @@ int sphfilt_batch_destroy(sphfilt_batch batch);
  * Filter every patch: outs[p] = Phi(Theta(ins[p])) (adjoint = 0) or
  * Theta(Phi(ins[p])) (adjoint != 0).
  *   ins, outs  host arrays of n_patches device pointers, each patch's fields
- *              in the layout of sphfilt_apply.  ins[p] == outs[p] for every
+ *              in the layout of sphfilt_apply and 16-byte aligned as there
+ *              (else SPHFILT_EINVAL).  ins[p] == outs[p] for every
  *              patch is the in-place fast path; an output that partially
  *              overlaps its own input, or overlaps any other patch's input
  *              or output, is SPHFILT_EINVAL.

@@ -463,6 +463,7 @@ int check_pointers(sphfilt_batch b, const double *const *ins, double *const *out
         if (!ins[p] || !outs[p]) return SPHFILT_EINVAL;
         const uintptr_t a = (uintptr_t)ins[p], o = (uintptr_t)outs[p];
         const size_t n = sizeof(double) * (size_t)b->patches[p].n_points;
+        if ((a | o) & 15) return SPHFILT_EINVAL;                           // 16-byte accesses
         if (a != o && a < o + n && o < a + n) return SPHFILT_EINVAL;
         if (a != o) all_in = false;
     }

@@ -153,6 +153,7 @@ int check_call(sphfilt_plan p, const double *in, double *out)
     if (!p || !in || !out) return SPHFILT_EINVAL;
     const size_t bytes = sizeof(double) * (size_t)p->n_fields * p->n_r * p->n_theta * p->n_phi;
     const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+    if ((a | b) & 15) return SPHFILT_EINVAL;                               // 16-byte accesses
     if (a != b && a < b + bytes && b < a + bytes) return SPHFILT_EINVAL;   // partial overlap
     if (fault("launch")) return SPHFILT_EDEVICE;
     return SPHFILT_OK;
