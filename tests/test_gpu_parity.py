@@ -212,6 +212,34 @@ def test_partial_overlap_rejected(torch_gpu):
         plan.apply(a, out=b)
 
 
+def test_misaligned_pointers_rejected(torch_gpu):
+    # the theta pass moves two adjacent doubles per access: field pointers must
+    # be 16-byte aligned, checked on the host before anything is launched
+    from paper_2305_01537_amd.filter import Batch, SphfiltError
+    torch = torch_gpu
+    shape = (1, 4, 16, 32)
+    n = int(np.prod(shape))
+    plan = make_plan(shape, 1, 3.0)
+    buf = torch.zeros(2 * n + 2, dtype=torch.float64, device="cuda")
+    a = buf[1:1 + n].view(shape)
+    good = buf[n + 2:].view(shape)
+    assert a.data_ptr() % 16 == 8 and good.data_ptr() % 16 == 0
+    for call in (lambda: plan.apply(a), lambda: plan.apply(a, out=a), lambda: plan.apply(good, out=a),
+                 lambda: plan.apply_adjoint(a, out=a), lambda: plan.apply_theta(a, out=a),
+                 lambda: plan.apply_phi(a, out=a)):
+        with pytest.raises(SphfiltError) as err:
+            call()
+        assert err.value.code == -1
+    torch.cuda.synchronize()
+    plan.close()
+    batch = Batch([dict(n_fields=1, n_r=4, n_theta=16, n_phi=32, parity=np.array([1], dtype=np.int32),
+                        L=np.array([3.0]))])
+    with pytest.raises(SphfiltError) as err:
+        batch.apply([a], outs=[a])
+    assert err.value.code == -1
+    batch.close()
+
+
 def test_empty_and_tiny_grids(torch_gpu):
     # a single shell and a single field; the phi item list is shorter than one workgroup
     rng = np.random.default_rng(9)
