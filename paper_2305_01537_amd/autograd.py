@@ -21,13 +21,20 @@ from torch.utils.checkpoint import checkpoint as _checkpoint
 from .filter import Plan
 
 
+def _aligned(t: torch.Tensor) -> torch.Tensor:
+    """A contiguous tensor whose data starts on a 16-byte boundary, as the
+    library requires: a copy only for a view that starts mid-way."""
+    t = t.contiguous()
+    return t if t.data_ptr() % 16 == 0 else t.clone()
+
+
 class SphFilter(torch.autograd.Function):
     """y = F x on the GPU; the backward applies F^T through the adjoint kernels."""
 
     @staticmethod
     def forward(ctx, x: torch.Tensor, plan: Plan) -> torch.Tensor:
         ctx.plan = plan
-        x = x.contiguous()
+        x = _aligned(x)
         if plan.has_hybrid:
             th, ph = plan.decision_buffers(x.device)
             y = plan.apply_ex(x, theta_dec=th, phi_dec=ph, replay=False)
@@ -37,7 +44,7 @@ class SphFilter(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        g = grad_out.contiguous()
+        g = _aligned(grad_out)
         if ctx.plan.has_hybrid:
             th, ph = ctx.saved_tensors
             return ctx.plan.apply_ex(g, adjoint=True, theta_dec=th, phi_dec=ph, replay=True), None

@@ -58,6 +58,25 @@ def test_autograd_uses_the_adjoint(env):
     assert torch.equal(x.grad, ref)
 
 
+def test_autograd_takes_views_that_start_mid_way(env):
+    # the library wants 16-byte aligned fields; the autograd layer copies a
+    # view that starts at an odd double (input and incoming gradient alike)
+    torch, w, plans = env
+    from paper_2305_01537_amd.autograd import sph_filter
+    plan = plans[3.0]
+    n = int(np.prod(w.shape))
+    rng = np.random.default_rng(53)
+    xb = torch.from_numpy(rng.standard_normal(n + 1)).cuda().requires_grad_(True)
+    gb = torch.from_numpy(rng.standard_normal(n + 1)).cuda()
+    x, g = xb[1:].view(w.shape), gb[1:].view(w.shape)
+    assert x.data_ptr() % 16 == 8 and g.data_ptr() % 16 == 8
+    y = sph_filter(x, plan)
+    y.backward(g)
+    assert torch.equal(y.detach(), plan.apply(x.detach().clone()))
+    assert torch.equal(xb.grad[1:].view(w.shape), plan.apply_adjoint(g.clone()))
+    assert float(xb.grad[0]) == 0.0
+
+
 def _loss_and_grad(torch, x, t, plan, K, checkpoint):
     from paper_2305_01537_amd.autograd import filter_chain
     xv = x.clone().requires_grad_(True)
