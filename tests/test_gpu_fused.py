@@ -3,11 +3,10 @@
 On grids with n_phi = 2 n_theta <= 128 a plan runs every shell whose theta
 lines and rings are all filtered through one kernel that keeps the shell in
 LDS between the two passes, in one launch with the ring pairs of the other
-shells.  It runs the same line transforms with the same pairing as the
-two-pass path, so the two agree to rounding (the compiler contracts
-multiply-adds into FMAs differently in different kernels: about one ulp), and
-both match the oracle; in place and out of place run the same kernel and are
-bitwise equal.  The shapes
+shells.  It runs the same line transforms as the two-pass path, packing other
+meridian pairs into its complex theta lines (k and k + N/4, where the two-pass
+kernel packs adjacent pairs), so the two agree to rounding, and both match the
+oracle; in place and out of place run the same kernel and are bitwise equal.  The shapes
 leave the number of fused shells ragged against the shells one workgroup takes
 (8 at n_phi = 32, 2 at 64, 1 at 128) and mix fused shells with shells that
 only the phi pass touches and shells that are left alone.
