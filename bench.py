@@ -34,7 +34,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "share_paper_cutoff_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2305_01537_amd", "csrc", f)
-                  for f in ("kernels.hip", "line_filter.h", "fft_core.h", "sphfilt_internal.h")]
+                  for f in ("kernels.hip", "kernels_theta.hip", "kernels_phi.hip", "line_filter.h",
+                            "fft_core.h", "sphfilt_internal.h")]
 
 
 def code_tokens(text):

@@ -1,4 +1,5 @@
-// batch_internal.h -- types shared by the batch host code and batch.hip.
+// batch_internal.h -- types shared by the batch host code and the batch
+// kernels (batch.hip, batch_kernels.h and its four instance files).
 #pragma once
 #include "sphfilt_internal.h"
 
@@ -43,6 +44,37 @@ struct BatchPatchDev {
     int32_t hybrid;       // some field of the patch is hybrid
     int32_t pad;
 };
+
+// Arguments of the batch kernel (see batch_kernels.h).
+struct BatchArgs {
+    const BatchWork *work;
+    int n_work;
+    const BatchPatchDev *patches;
+    const double *const *ins;
+    double *const *outs;
+    const ThetaItem *th;
+    const PhiItem *ph;
+    const double *fc;
+    const int *shells;
+    int *counters;
+    const int *need;
+    int *ticket;
+    int *error;
+    const double *eneg;
+    int use_deps;
+    int spin_limit;
+};
+
+// The four kernel instances (HYB, MIXED), each in its own translation unit:
+// grid > 0 persistent workgroups, else one workgroup per item.
+hipError_t launch_batch_plain(int grid, const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_hybrid(int grid, const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_mixed(int grid, const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_mixed_hybrid(int grid, const BatchArgs &a, hipStream_t s);
+int blocks_per_cu_plain();
+int blocks_per_cu_hybrid();
+int blocks_per_cu_mixed();
+int blocks_per_cu_mixed_hybrid();
 
 hipError_t launch_batch_reset(int *counters, int n_counters, int *tickets, int n_tickets,
                               int *error, hipStream_t s);

@@ -1,63 +1,14 @@
-// kernels.hip -- per-plan kernels of the double FFT filter (arXiv:2305.01537,
-// Sec. II.B) for gfx950, FP64: one launch per pass over a plan's item list.
+// kernels.hip -- the fused shell kernel of the per-plan path and the launch
+// shapes of the pass kernels (the theta and phi kernels are in
+// kernels_theta.hip and kernels_phi.hip), double FFT filter (arXiv:2305.01537,
+// Sec. II.B) for gfx950, FP64.
 // The work of a workgroup is done by the workers in line_filter.h, which the
 // batched persistent kernel (batch.hip) shares: the same arithmetic per line
 // (bit for bit where the compiler contracts multiply-adds the same way in
 // both kernels, to rounding otherwise).
 #include "line_filter.h"
 
-// The hybrid-capable theta and phi kernels need a little more than 256
-// registers at N = 256: two waves per SIMD with a small spill (68-84 bytes per
-// lane) beat one wave without (the share with 8 hybrid fields: 0.81 against
-// 1.25 ms per forward filter).
-
 namespace sphfilt {
-
-// Waves per SIMD a pass kernel asks the compiler for (it caps the registers
-// per lane at 512 / waves).  The hybrid-capable instances: two, where two
-// workgroups' line scratch (a whole spectrum per line) fits in LDS, else one.
-// The plain instances: no target (they fit two or more waves by themselves).
-template <int N, int LINES, bool HYB>
-constexpr int pass_waves()
-{
-    constexpr int bytes = 8 * LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
-    return HYB && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
-}
-
-// theta-pass: workgroup b handles shell group g = b / tiles (S = C / cp shells
-// of the item list) and meridian tile b % tiles.
-template <int N, int C, bool HYB>
-__global__ __launch_bounds__(C * Split<N>::N2) __attribute__((amdgpu_waves_per_eu(pass_waves<N, C, HYB>()))) void theta_kernel(
-    const double *in, double *out, const ThetaItem *__restrict__ items, int n_items, int cp_log2,
-    int tiles, int n_theta, int n_phi, const Twiddle *__restrict__ tw,
-    const double *__restrict__ eneg, HybridArgs h)
-{
-    constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-    __shared__ double lds[C * line_stride<N1, N2, HYB>()];
-    __shared__ double etab[N / 2 + 1];
-    __shared__ int flags[C];
-    const int group = blockIdx.x / tiles, tile = blockIdx.x % tiles;
-    const int per_group = C >> cp_log2;
-    const int first = group * per_group;
-    const int n_valid = min(per_group, n_items - first);
-    theta_block<N, C, HYB>(in, out, items + first, n_valid, cp_log2, tile, n_theta, n_phi, tw, eneg,
-                      lds, etab, flags, h, threadIdx.x);
-}
-
-// phi-pass: workgroup b handles ring pairs [b * LINES, b * LINES + LINES).
-template <int N, int LINES, bool HYB>
-__global__ __launch_bounds__(LINES * Split<N>::N2) __attribute__((amdgpu_waves_per_eu(pass_waves<N, LINES, HYB>()))) void phi_kernel(
-    const double *in, double *out, const PhiItem *__restrict__ items, int n_items, int n_theta,
-    const Twiddle *__restrict__ tw, const double *__restrict__ eneg, HybridArgs h)
-{
-    constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-    __shared__ double lds[LINES * line_stride<N1, N2, HYB>()];
-    __shared__ double etab[N / 2 + 1];
-    __shared__ int flags[LINES];
-    const int first = blockIdx.x * LINES;
-    phi_block<N, LINES, HYB>(in, out, items + first, min(LINES, n_items - first), n_theta, tw, eneg,
-                        lds, etab, flags, h, threadIdx.x);
-}
 
 // Fused shells and, in the same grid, ring pairs of the other shells: blocks
 // [0, shell_groups) run shell_block on `shells`, the rest run phi_block
@@ -151,105 +102,8 @@ bool phi_shape_ok(int n_line, int lines)
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// fused shell launcher
 // ---------------------------------------------------------------------------
-template <int N>
-static hipError_t theta_go(int cols, const double *in, double *out, const ThetaItem *items,
-                           int n_items, int n_theta, int n_phi, const Twiddle *tw,
-                           const double *eneg, const HybridArgs &h, hipStream_t s)
-{
-    constexpr int C = lines_per_256<N>();
-    const int cp_log2 = ilog2_int(cols);
-    const int per_group = C / cols;
-    const int tiles = (n_phi / 2) / (2 * cols);
-    const int groups = (n_items + per_group - 1) / per_group;
-    const dim3 grid((unsigned)(groups * tiles)), block(256);
-    // the hybrid-capable variant only when the plan has hybrid fields: its
-    // detector and two-kind mask cost registers the plain filter does not need
-    if (h.present)
-        theta_kernel<N, C, true><<<grid, block, 0, s>>>(in, out, items, n_items, cp_log2, tiles,
-                                                        n_theta, n_phi, tw, eneg, h);
-    else
-        theta_kernel<N, C, false><<<grid, block, 0, s>>>(in, out, items, n_items, cp_log2, tiles,
-                                                         n_theta, n_phi, tw, eneg, h);
-    return hipGetLastError();
-}
-
-hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
-                        const ThetaItem *items, int n_items, int n_theta, int n_phi,
-                        const Twiddle *tw, const double *eneg, const HybridArgs &h,
-                        hipStream_t s)
-{
-    if (n_items <= 0) return hipSuccess;
-    if (!theta_shape_ok(n_line, cols, n_phi) || n_line != 2 * n_theta) return hipErrorInvalidValue;
-    switch (n_line) {
-    case 32: return theta_go<32>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    case 48: return theta_go<48>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    case 64: return theta_go<64>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    case 80: return theta_go<80>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    case 96: return theta_go<96>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    case 128: return theta_go<128>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    case 160: return theta_go<160>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    case 192: return theta_go<192>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    case 256: return theta_go<256>(cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int N, int LINES>
-static hipError_t phi_go(const double *in, double *out, const PhiItem *items, int n_items,
-                         int n_theta, const Twiddle *tw, const double *eneg, const HybridArgs &h,
-                         hipStream_t s)
-{
-    if constexpr (LINES * Split<N>::N2 > 256 || LINES * Split<N>::N2 < 16) {
-        return hipErrorInvalidValue;
-    } else {
-        const dim3 grid((unsigned)((n_items + LINES - 1) / LINES)), block(LINES * Split<N>::N2);
-        if (h.present)
-            phi_kernel<N, LINES, true><<<grid, block, 0, s>>>(in, out, items, n_items, n_theta, tw,
-                                                              eneg, h);
-        else
-            phi_kernel<N, LINES, false><<<grid, block, 0, s>>>(in, out, items, n_items, n_theta, tw,
-                                                               eneg, h);
-        return hipGetLastError();
-    }
-}
-
-template <int N>
-static hipError_t phi_lines(int lines, const double *in, double *out, const PhiItem *items,
-                            int n_items, int n_theta, const Twiddle *tw, const double *eneg,
-                            const HybridArgs &h, hipStream_t s)
-{
-    switch (lines) {
-    case 4: return phi_go<N, 4>(in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 8: return phi_go<N, 8>(in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 16: return phi_go<N, 16>(in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 32: return phi_go<N, 32>(in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 64: return phi_go<N, 64>(in, out, items, n_items, n_theta, tw, eneg, h, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_phi(int n_line, int lines, const double *in, double *out, const PhiItem *items,
-                      int n_items, int n_theta, const Twiddle *tw, const double *eneg,
-                      const HybridArgs &h, hipStream_t s)
-{
-    if (n_items <= 0) return hipSuccess;
-    if (!phi_shape_ok(n_line, lines)) return hipErrorInvalidValue;
-    switch (n_line) {
-    case 32: return phi_lines<32>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 48: return phi_lines<48>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 64: return phi_lines<64>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 80: return phi_lines<80>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 96: return phi_lines<96>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 128: return phi_lines<128>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 160: return phi_lines<160>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 192: return phi_lines<192>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    case 256: return phi_lines<256>(lines, in, out, items, n_items, n_theta, tw, eneg, h, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 bool shell_fusable(int n_theta, int n_phi)
 {
     return n_phi == 2 * n_theta && (n_phi == 32 || n_phi == 64 || n_phi == 128);

@@ -825,3 +825,23 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
 }
 
 }  // namespace sphfilt
+
+namespace sphfilt {
+
+// The hybrid-capable theta and phi kernels need a little more than 256
+// registers at N = 256: two waves per SIMD with a small spill (68-84 bytes per
+// lane) beat one wave without (the share with 8 hybrid fields: 0.81 against
+// 1.25 ms per forward filter).
+
+// Waves per SIMD a pass kernel asks the compiler for (it caps the registers
+// per lane at 512 / waves).  The hybrid-capable instances: two, where two
+// workgroups' line scratch (a whole spectrum per line) fits in LDS, else one.
+// The plain instances: no target (they fit two or more waves by themselves).
+template <int N, int LINES, bool HYB>
+constexpr int pass_waves()
+{
+    constexpr int bytes = 8 * LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>();
+    return HYB && 2 * bytes <= 160 * 1024 - 4096 ? 2 : 1;
+}
+
+}  // namespace sphfilt

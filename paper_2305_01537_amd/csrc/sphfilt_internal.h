@@ -48,7 +48,8 @@ struct Twiddle {
     double re, im;         // exp(-2 pi i j / N)
 };
 
-// Launchers (kernels.hip).  All return hipSuccess or the launch error.
+// Launchers (kernels_theta.hip, kernels_phi.hip, kernels.hip).  All return
+// hipSuccess or the launch error.
 // theta: n_items shells, each split in tiles of 2*cols meridian columns.
 // eneg: e^{-k} for k in [0, kExpTable), used by the exponential mask.
 hipError_t launch_theta(int n_line, int cols, const double *in, double *out,
