@@ -344,8 +344,11 @@ int sphfilt_batch_set_schedule(sphfilt_batch batch, int split, int workgroups_pe
 int sphfilt_batch_get_schedule(sphfilt_batch batch, int *split, int *workgroups_per_cu,
                                double *tuned_us);
 
-/* Device error word of the last call (synchronises the device): 0, or 1 if a
- * second-pass item gave up waiting (a library bug; results are invalid). */
+/* Device error word of the batch's last call (synchronises the device): 0,
+ * or 1 if a second-pass item gave up waiting for its shells (a library bug;
+ * such an item stores nothing, so its lines hold the first pass's result and
+ * the call's output is invalid).  Callers that need the guarantee poll this
+ * after their calls. */
 int sphfilt_batch_status(sphfilt_batch batch, int *device_error);
 
 /* Work and traffic figures summed over the batch's patches (host only);

@@ -55,6 +55,7 @@ struct ModeWork {
 
 struct GraphEntry {
     int mode = 0, split = 0, wpc = 0;
+    int wait_fault = 0;       // captured with the forced give-up of SPHFILT_FAULT=wait
     std::vector<const double *> ins;
     std::vector<double *> outs;
     const double **d_ins = nullptr;
@@ -62,6 +63,15 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;
+};
+
+// Where a call's counters, tickets, error word and pointer tables live.
+struct CallScratch {
+    int *counters;
+    int *tickets;
+    int *error;
+    const double *const *ins;
+    double *const *outs;
 };
 
 }  // namespace
@@ -332,46 +342,42 @@ int effective_wpc(sphfilt_batch b, int wpc)
     return wpc == 0 || wpc > b->max_wpc ? b->max_wpc : wpc;
 }
 
-// Record the reset kernel and the persistent kernel(s) on the capture stream.
-int record(sphfilt_batch b, const ModeWork &m, const GraphEntry &g, hipStream_t s)
+// SPHFILT_FAULT=wait (tests only): every wait target is raised by one and the
+// spin is cut short, so that second-pass items of the one-kernel schedule give
+// up at once; the kernels still run to their end.
+constexpr int kFaultSpinLimit = 64;
+
+// Enqueue the reset kernel and the persistent kernel(s) of `m` on stream s
+// (the capture stream).
+int record(sphfilt_batch b, const ModeWork &m, int split, int wpc_setting, const CallScratch &sc,
+           int wait_fault, hipStream_t s)
 {
-    const int wpc = effective_wpc(b, g.wpc);
+    const int wpc = effective_wpc(b, wpc_setting);
     const int grid = wpc < 0 ? 0 : wpc * b->n_cu;
-    hipError_t e = launch_batch_reset(b->d_counters, b->n_shells_total, b->d_tickets, 3, b->d_error, s);
+    const int spin = wait_fault ? kFaultSpinLimit : kSpinLimit, bias = wait_fault ? 1 : 0;
+    auto go = [&](int first, int n, int *ticket, int deps, hipStream_t st) {
+        return launch_batch(grid, m.d_work + first, n, b->d_patches, sc.ins, sc.outs, b->d_th,
+                            b->d_ph, b->d_fc, m.d_shells, sc.counters, m.d_need, ticket, sc.error,
+                            b->d_eneg, deps, spin, bias, b->variant, st);
+    };
+    hipError_t e = launch_batch_reset(sc.counters, b->n_shells_total, sc.tickets, 3, sc.error, s);
     if (e != hipSuccess) return SPHFILT_EDEVICE;
-    if (g.split == 2 && m.n_indep > 0) {
+    if (split == 2 && m.n_indep > 0) {
         // fork: the independent second-pass items on the side stream, the
         // first pass and then the dependent second-pass items here; join
         const int dep0 = m.n_first + m.n_indep;
         e = hipEventRecord(b->fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->side_stream, b->fork, 0);
-        if (e == hipSuccess)
-            e = launch_batch(grid, m.d_work + m.n_first, m.n_indep, b->d_patches, g.d_ins, g.d_outs,
-                             b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
-                             b->d_tickets + 2, b->d_error, b->d_eneg, 0, kSpinLimit, b->variant,
-                             b->side_stream);
-        if (e == hipSuccess)
-            e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th,
-                             b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets,
-                             b->d_error, b->d_eneg, 0, kSpinLimit, b->variant, s);
-        if (e == hipSuccess)
-            e = launch_batch(grid, m.d_work + dep0, m.n_work - dep0, b->d_patches, g.d_ins, g.d_outs,
-                             b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
-                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->variant, s);
+        if (e == hipSuccess) e = go(m.n_first, m.n_indep, sc.tickets + 2, 0, b->side_stream);
+        if (e == hipSuccess) e = go(0, m.n_first, sc.tickets, 0, s);
+        if (e == hipSuccess) e = go(dep0, m.n_work - dep0, sc.tickets + 1, 0, s);
         if (e == hipSuccess) e = hipEventRecord(b->join, b->side_stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join, 0);
-    } else if (g.split) {
-        e = launch_batch(grid, m.d_work, m.n_first, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
-                         b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg,
-                         0, kSpinLimit, b->variant, s);
-        if (e == hipSuccess)
-            e = launch_batch(grid, m.d_work + m.n_first, m.n_work - m.n_first, b->d_patches, g.d_ins,
-                             g.d_outs, b->d_th, b->d_ph, b->d_fc, m.d_shells, b->d_counters, m.d_need,
-                             b->d_tickets + 1, b->d_error, b->d_eneg, 0, kSpinLimit, b->variant, s);
+    } else if (split) {
+        e = go(0, m.n_first, sc.tickets, 0, s);
+        if (e == hipSuccess) e = go(m.n_first, m.n_work - m.n_first, sc.tickets + 1, 0, s);
     } else {
-        e = launch_batch(grid, m.d_work, m.n_work, b->d_patches, g.d_ins, g.d_outs, b->d_th, b->d_ph,
-                         b->d_fc, m.d_shells, b->d_counters, m.d_need, b->d_tickets, b->d_error, b->d_eneg, 1,
-                         kSpinLimit, b->variant, s);
+        e = go(0, m.n_work, sc.tickets, 1, s);
     }
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
@@ -381,8 +387,10 @@ int get_graph(sphfilt_batch b, int mode, const double *const *ins, double *const
               GraphEntry **out)
 {
     const size_t P = b->patches.size();
+    const int wait_fault = fault("wait") ? 1 : 0;
     for (GraphEntry &g : b->graphs) {
-        if (g.mode != mode || g.split != b->split || g.wpc != b->wpc) continue;
+        if (g.mode != mode || g.split != b->split || g.wpc != b->wpc || g.wait_fault != wait_fault)
+            continue;
         if (!std::equal(g.ins.begin(), g.ins.end(), ins) || !std::equal(g.outs.begin(), g.outs.end(), outs))
             continue;
         g.last_use = ++b->clock;
@@ -401,6 +409,7 @@ int get_graph(sphfilt_batch b, int mode, const double *const *ins, double *const
     g.mode = mode;
     g.split = b->split;
     g.wpc = b->wpc;
+    g.wait_fault = wait_fault;
     g.ins.assign(ins, ins + P);
     g.outs.assign(outs, outs + P);
     rc = upload(&g.d_ins, g.ins);
@@ -409,7 +418,9 @@ int get_graph(sphfilt_batch b, int mode, const double *const *ins, double *const
         hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) rc = SPHFILT_EDEVICE;
         if (!rc) {
-            const int rr = record(b, b->modes[mode], g, b->capture_stream);
+            const CallScratch sc{b->d_counters, b->d_tickets, b->d_error, g.d_ins, g.d_outs};
+            const int rr = record(b, b->modes[mode], g.split, g.wpc, sc, g.wait_fault,
+                                  b->capture_stream);
             e = hipStreamEndCapture(b->capture_stream, &g.graph);
             rc = rr ? rr : (e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE);
         }
@@ -437,6 +448,17 @@ void free_work(sphfilt_batch b)
         if (m.d_need) (void)hipFree(m.d_need);
         m = ModeWork{};
     }
+}
+
+// Build the work lists of all four modes (forward/adjoint x in/out of place)
+// up front.
+int ensure_modes(sphfilt_batch b)
+{
+    for (int mode = 0; mode < 4; ++mode) {
+        const int rc = build_mode(b, mode);
+        if (rc) return rc;
+    }
+    return SPHFILT_OK;
 }
 
 void free_batch(sphfilt_batch b)
@@ -591,6 +613,8 @@ int tune(sphfilt_batch b, const char *cache_path)
     b->split = best_split;
     b->wpc = best_wpc;
     b->tuned_us = best;
+    rc = ensure_modes(b);
+    if (rc) return rc;
     if (cache_path && !cache_store(cache_path, hex64(b->signature), b->arch, best_split, best_wpc,
                                    best_fused, best))
         return SPHFILT_EINVAL;
@@ -713,6 +737,8 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
             rc = tune(b, tune_cache_path);
         }
     }
+    // the work lists of every mode
+    if (!rc) rc = ensure_modes(b);
     if (rc) {
         free_batch(b);
         delete b;
@@ -809,7 +835,7 @@ int sphfilt_batch_set_fused(sphfilt_batch batch, int enable)
     if (hipDeviceSynchronize() != hipSuccess) return SPHFILT_EDEVICE;
     free_work(batch);
     batch->fused = enable;
-    return SPHFILT_OK;
+    return ensure_modes(batch);
 }
 
 int sphfilt_batch_get_fused(sphfilt_batch batch, int *enable, int *shells_fused)

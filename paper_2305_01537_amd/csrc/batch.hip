@@ -33,11 +33,11 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
                         const double *const *ins, double *const *outs, const ThetaItem *th,
                         const PhiItem *ph, const double *fc, const int *shells, int *counters,
                         const int *need, int *ticket, int *error, const double *eneg, int use_deps,
-                        int spin_limit, int variant, hipStream_t s)
+                        int spin_limit, int need_bias, int variant, hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
     const BatchArgs a{work, n_work, patches, ins, outs, th, ph, fc, shells, counters,
-                      need, ticket, error, eneg, use_deps, spin_limit};
+                      need, ticket, error, eneg, use_deps, spin_limit, need_bias};
     switch (variant & 3) {
     case 0: return launch_batch_plain(grid, a, s);
     case kBatchHybrid: return launch_batch_hybrid(grid, a, s);

@@ -63,6 +63,7 @@ struct BatchArgs {
     const double *eneg;
     int use_deps;
     int spin_limit;
+    int need_bias;        // added to every wait target (0; 1 only to force a give-up in tests)
 };
 
 // The four kernel instances (HYB, MIXED), each in its own translation unit:
@@ -89,9 +90,10 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
                         const PhiItem *ph, const double *fc, const int *shells, int *counters,
                         const int *need,
                         int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
-                        int variant, hipStream_t s);
+                        int need_bias, int variant, hipStream_t s);
 // Resident 256-lane workgroups of the persistent batch kernel instance
 // `variant` per compute unit.
 int batch_blocks_per_cu(int variant);
+
 
 }  // namespace sphfilt

@@ -109,33 +109,40 @@ __device__ __forceinline__ void fused_item(const BatchWork &w, const BatchPatchD
 
 // One work item k (workgroup-uniform): wait for its shells (second pass),
 // filter, signal its shells (first pass).
+// gave_up: a workgroup-shared word for the outcome of the wait.
 template <bool HYB, bool MIXED>
 __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, double *lds,
-                                         double *etab, int *flags)
+                                         double *etab, int *flags, int *gave_up)
 {
     const BatchWork w = a.work[k];
     const BatchPatchDev pd = a.patches[w.patch];
 
     if (a.use_deps && w.second) {
         // wait until every first-pass item writing these shells is done:
-        // relaxed polling, then one device-scope acquire
+        // relaxed polling, then one device-scope acquire.  If the bounded
+        // spin gives up, the error word is set and the item is skipped (its
+        // output is left as the first pass wrote it).
         if (lane == 0) {
-            for (int i = 0; i < w.n_shells; ++i) {
+            int late = 0;
+            for (int i = 0; i < w.n_shells && !late; ++i) {
                 const int s = a.shells[w.shell_off + i];
-                const int target = a.need[s];
+                const int target = a.need[s] + a.need_bias;
                 int spins = 0;
                 while (__hip_atomic_load(a.counters + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                        target) {
                     __builtin_amdgcn_s_sleep(4);
                     if (++spins > a.spin_limit) {
                         atomicOr(a.error, 1);
+                        late = 1;
                         break;
                     }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            *gave_up = late;
         }
         __syncthreads();
+        if (*gave_up) return;       // workgroup-uniform
     }
 
     const double *src = w.second ? a.outs[w.patch] : a.ins[w.patch];
@@ -229,9 +236,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(oneshot_wav
     __shared__ double lds[batch_lds<HYB, MIXED>()];
     __shared__ double etab[129];
     __shared__ int flags[64];
-    __shared__ int cur;
+    __shared__ int cur, gave_up;
     const int k = a.use_deps ? next_ticket(a.ticket, &cur) : (int)blockIdx.x;
-    if (k < a.n_work) run_item<HYB, MIXED>(a, k, threadIdx.x, lds, etab, flags);
+    if (k < a.n_work) run_item<HYB, MIXED>(a, k, threadIdx.x, lds, etab, flags, &gave_up);
 }
 
 // Persistent form: a fixed grid; each workgroup takes tickets until the list
@@ -247,13 +254,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_
     __shared__ double lds[batch_lds<HYB, MIXED>()];
     __shared__ double etab[129];
     __shared__ int flags[64];
-    __shared__ int cur;
+    __shared__ int cur, gave_up;
     for (;;) {
         const int k = next_ticket(a.ticket, &cur);
         if (k >= a.n_work) break;
         unsigned lane;
         asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((unsigned)threadIdx.x));
-        run_item<HYB, MIXED>(a, k, (int)lane, lds, etab, flags);
+        run_item<HYB, MIXED>(a, k, (int)lane, lds, etab, flags, &gave_up);
     }
 }
 

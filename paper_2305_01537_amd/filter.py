@@ -287,8 +287,11 @@ class Batch:
     def __len__(self):
         return len(self.shapes)
 
-    def apply(self, xs, outs=None, adjoint: bool = False, stream=None):
-        """outs[p] = F xs[p] (or F^T with adjoint=True); outs=xs filters in place."""
+    @property
+    def handle(self):
+        return self._h
+
+    def _pointers(self, xs, outs):
         import torch
         if len(xs) != len(self.shapes):
             raise ValueError(f"expected {len(self.shapes)} tensors")
@@ -302,9 +305,22 @@ class Batch:
         n = len(xs)
         ins_p = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         outs_p = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        return outs, ins_p, outs_p
+
+    def apply(self, xs, outs=None, adjoint: bool = False, stream=None, check: bool = False):
+        """outs[p] = F xs[p] (or F^T with adjoint=True); outs=xs filters in place.
+
+        check=True synchronises the device after the call and raises if the
+        batch kernel flagged an error (a second-pass item that gave up waiting
+        for its shells; see status())."""
+        outs, ins_p, outs_p = self._pointers(xs, outs)
         rc = self._lib.sphfilt_batch_apply(self._h, ins_p, outs_p, 1 if adjoint else 0,
                                            _stream_handle(xs[0], stream))
         _lib.check("sphfilt_batch_apply", rc)
+        if check:
+            err = self.status()
+            if err:
+                raise SphfiltError("sphfilt_batch_apply (device error word)", _lib.EDEVICE)
         return outs
 
     def tune(self, cache_path: Optional[str] = None):
