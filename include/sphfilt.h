@@ -317,6 +317,32 @@ int sphfilt_batch_destroy(sphfilt_batch batch);
 int sphfilt_batch_apply(sphfilt_batch batch, const double *const *ins, double *const *outs,
                         int adjoint, void *stream);
 
+/*
+ * For callers that cannot allocate device memory during a call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same filter as sphfilt_batch_apply, with the same arguments, checks and
+ * results (the same kernels on the same work lists), that allocates nothing.
+ * The batch's tables and work lists are built by sphfilt_batch_create (and
+ * rebuilt by sphfilt_batch_tune / sphfilt_batch_set_fused); the per-call
+ * counters, tickets, error word and the patch pointer tables live in a
+ * statically allocated device array of the library, about 1.02 MiB
+ * (256 B + 16 KiB of pointer tables + 1 MiB of counters), one copy per device,
+ * held until the process ends.  The kernels are enqueued directly on `stream`
+ * (no graph is captured; split = 2 schedules still fork onto the batch's own
+ * stream and join back).
+ * Limits: at most 1024 patches and 262144 shells (n_fields * n_r summed over
+ * the patches), else SPHFILT_EUNSUPPORTED.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (on different streams, from any batch) race and give wrong
+ * results; calls must be ordered on one stream, or synchronised.  The array
+ * keeps the last call's contents; each call clears what must start at zero
+ * (counters, tickets, error word) with a kernel before its filter kernels.
+ * sphfilt_batch_status reports this array's error word when the batch's last
+ * call was this one (valid until the next allocation-free call on the device).
+ */
+int sphfilt_batch_apply_noalloc(sphfilt_batch batch, const double *const *ins,
+                                double *const *outs, int adjoint, void *stream);
+
 /* Run the autotuner now (see sphfilt_batch_create); tune_cache_path may be
  * NULL to tune without recording.  Synchronous. */
 int sphfilt_batch_tune(sphfilt_batch batch, const char *tune_cache_path);

@@ -63,6 +63,9 @@ SIGNATURES = {
     "sphfilt_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sphfilt_batch_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
+    "sphfilt_batch_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                                   ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                                   ctypes.c_void_p]),
     "sphfilt_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "sphfilt_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "sphfilt_batch_get_schedule": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_double_p]),

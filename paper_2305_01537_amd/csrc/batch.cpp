@@ -65,7 +65,9 @@ struct GraphEntry {
     uint64_t last_use = 0;
 };
 
-// Where a call's counters, tickets, error word and pointer tables live.
+// Where a call's counters, tickets, error word and pointer tables live: the
+// batch's own device memory (graph path) or the static scratch array of the
+// allocation-free entry point.
 struct CallScratch {
     int *counters;
     int *tickets;
@@ -104,6 +106,8 @@ struct sphfilt_batch_s {
     hipStream_t capture_stream = nullptr;
     hipStream_t side_stream = nullptr;    // parallel branch of split = 2 graphs
     hipEvent_t fork = nullptr, join = nullptr;
+    unsigned char *noalloc = nullptr;     // device address of the static scratch array
+    int last_noalloc = 0;                 // the last call went through the allocation-free entry
 };
 
 namespace {
@@ -348,7 +352,7 @@ int effective_wpc(sphfilt_batch b, int wpc)
 constexpr int kFaultSpinLimit = 64;
 
 // Enqueue the reset kernel and the persistent kernel(s) of `m` on stream s
-// (the capture stream).
+// (a capture stream, or the caller's stream for the allocation-free call).
 int record(sphfilt_batch b, const ModeWork &m, int split, int wpc_setting, const CallScratch &sc,
            int wait_fault, hipStream_t s)
 {
@@ -451,7 +455,7 @@ void free_work(sphfilt_batch b)
 }
 
 // Build the work lists of all four modes (forward/adjoint x in/out of place)
-// up front.
+// up front, so that no call has to allocate them.
 int ensure_modes(sphfilt_batch b)
 {
     for (int mode = 0; mode < 4; ++mode) {
@@ -516,7 +520,35 @@ int launch(sphfilt_batch b, const double *const *ins, double *const *outs, int a
     GraphEntry *g = nullptr;
     rc = get_graph(b, mode, ins, outs, &g);
     if (rc) return rc;
+    b->last_noalloc = 0;
     return hipGraphLaunch(g->exec, stream) == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
+}
+
+// The allocation-free call: the batch's work lists (built at creation) and the
+// static scratch array; the kernels are launched directly on the caller's
+// stream (no graph, no allocation, no library routine that allocates).
+int launch_noalloc(sphfilt_batch b, const double *const *ins, double *const *outs, int adjoint,
+                   hipStream_t stream)
+{
+    bool inplace = false;
+    int rc = check_pointers(b, ins, outs, &inplace);
+    if (rc) return rc;
+    if ((int)b->patches.size() > kNoAllocMaxPatches || b->n_shells_total > kNoAllocMaxShells)
+        return SPHFILT_EUNSUPPORTED;
+    if (!b->noalloc && noalloc_scratch(b->device, &b->noalloc) != hipSuccess) return SPHFILT_EDEVICE;
+    if (fault("launch")) return SPHFILT_EDEVICE;
+    const int mode = (adjoint ? 1 : 0) | (inplace ? 2 : 0);
+    const ModeWork &m = b->modes[mode];
+    if (!m.built) return SPHFILT_EINVAL;      // rebuilt by every call that drops them
+    unsigned char *base = b->noalloc;
+    int *head = reinterpret_cast<int *>(base);
+    const CallScratch sc{reinterpret_cast<int *>(base + kNoAllocCounterOffset), head, head + 3,
+                         reinterpret_cast<const double *const *>(base + kNoAllocPtrOffset),
+                         reinterpret_cast<double *const *>(base + kNoAllocPtrOffset) + kNoAllocMaxPatches};
+    if (noalloc_set_pointers(base, ins, outs, (int)b->patches.size(), stream) != hipSuccess)
+        return SPHFILT_EDEVICE;
+    b->last_noalloc = 1;
+    return record(b, m, b->split, b->wpc, sc, fault("wait") ? 1 : 0, stream);
 }
 
 // Time the current schedule on scratch fields: median of `reps` graph launches.
@@ -737,8 +769,13 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
             rc = tune(b, tune_cache_path);
         }
     }
-    // the work lists of every mode
+    // the work lists of every mode, and the device address of the static
+    // scratch array of the allocation-free entry point (looked up once per
+    // device, with the batch's device current)
+    // (a failed lookup is retried by the first allocation-free call, which
+    // reports it; the other entry points do not need the array)
     if (!rc) rc = ensure_modes(b);
+    if (!rc && noalloc_scratch(b->device, &b->noalloc) != hipSuccess) b->noalloc = nullptr;
     if (rc) {
         free_batch(b);
         delete b;
@@ -767,6 +804,15 @@ int sphfilt_batch_apply(sphfilt_batch batch, const double *const *ins, double *c
     DeviceGuard g(batch->device);
     if (!g.ok) return SPHFILT_EDEVICE;
     return launch(batch, ins, outs, adjoint, (hipStream_t)stream);
+}
+
+int sphfilt_batch_apply_noalloc(sphfilt_batch batch, const double *const *ins,
+                                double *const *outs, int adjoint, void *stream)
+{
+    if (!batch) return SPHFILT_EINVAL;
+    DeviceGuard g(batch->device);
+    if (!g.ok) return SPHFILT_EDEVICE;
+    return launch_noalloc(batch, ins, outs, adjoint, (hipStream_t)stream);
 }
 
 int sphfilt_batch_tune(sphfilt_batch batch, const char *tune_cache_path)
@@ -803,7 +849,12 @@ int sphfilt_batch_status(sphfilt_batch batch, int *device_error)
     DeviceGuard g(batch->device);
     if (!g.ok) return SPHFILT_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return SPHFILT_EDEVICE;
-    if (hipMemcpy(device_error, batch->d_error, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    // the error word of the last call: the batch's own, or the static array's
+    // after an allocation-free call (valid until another such call on the device)
+    const int *word = batch->last_noalloc && batch->noalloc
+                          ? reinterpret_cast<const int *>(batch->noalloc) + 3
+                          : batch->d_error;
+    if (hipMemcpy(device_error, word, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return SPHFILT_EDEVICE;
     return SPHFILT_OK;
 }

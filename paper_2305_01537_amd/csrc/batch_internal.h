@@ -95,5 +95,24 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
 // `variant` per compute unit.
 int batch_blocks_per_cu(int variant);
 
+// ---- the allocation-free entry point's device scratch (batch.hip) --------
+// One statically allocated array per device holds the batch kernel's
+// counters, tickets, error word and the per-call pointer tables:
+//   ints [0, 3) tickets, int 3 the error word, then (from byte 256) the
+//   input and output pointer tables (kNoAllocMaxPatches pointers each), then
+//   kNoAllocMaxShells shell counters.
+constexpr int kNoAllocMaxPatches = 1024;
+constexpr int kNoAllocMaxShells = 1 << 18;
+constexpr size_t kNoAllocPtrOffset = 256;
+constexpr size_t kNoAllocCounterOffset = kNoAllocPtrOffset + 2 * sizeof(void *) * kNoAllocMaxPatches;
+constexpr size_t kNoAllocScratchBytes = kNoAllocCounterOffset + sizeof(int) * (size_t)kNoAllocMaxShells;
+// Device address of the scratch array on the current device (looked up with
+// hipGetSymbolAddress on the first call per device, then cached); returns
+// hipSuccess or the lookup's error.
+hipError_t noalloc_scratch(int device, unsigned char **out);
+// Write n pointer pairs into the scratch tables, from index `first`, with
+// kernels on stream s (the pointers travel as kernel arguments).
+hipError_t noalloc_set_pointers(unsigned char *scratch, const double *const *ins,
+                                double *const *outs, int n, hipStream_t s);
 
 }  // namespace sphfilt

@@ -323,6 +323,16 @@ class Batch:
                 raise SphfiltError("sphfilt_batch_apply (device error word)", _lib.EDEVICE)
         return outs
 
+    def apply_noalloc(self, xs, outs=None, adjoint: bool = False, stream=None):
+        """The same filter through sphfilt_batch_apply_noalloc: no device
+        allocation during the call (the per-call state lives in the library's
+        static device array; calls on one device must not overlap)."""
+        outs, ins_p, outs_p = self._pointers(xs, outs)
+        rc = self._lib.sphfilt_batch_apply_noalloc(self._h, ins_p, outs_p, 1 if adjoint else 0,
+                                                   _stream_handle(xs[0], stream))
+        _lib.check("sphfilt_batch_apply_noalloc", rc)
+        return outs
+
     def tune(self, cache_path: Optional[str] = None):
         path = None if cache_path is None else str(cache_path).encode()
         _lib.check("sphfilt_batch_tune", self._lib.sphfilt_batch_tune(self._h, path))

@@ -47,6 +47,7 @@ def test_launch_fault_gives_edevice(monkeypatch):
     assert lib.sphfilt_apply(plan.handle, xp, xp, stream) == _lib.EDEVICE
     assert lib.sphfilt_apply_adjoint(plan.handle, xp, xp, stream) == _lib.EDEVICE
     assert lib.sphfilt_batch_apply(batch.handle, ptrs, ptrs, 0, stream) == _lib.EDEVICE
+    assert lib.sphfilt_batch_apply_noalloc(batch.handle, ptrs, ptrs, 0, stream) == _lib.EDEVICE
     monkeypatch.delenv("SPHFILT_FAULT")
     torch.cuda.synchronize()
     # nothing was enqueued: the fields are untouched, and calls work again
@@ -60,7 +61,8 @@ def test_launch_fault_gives_edevice(monkeypatch):
     batch.close()
 
 
-def test_batch_wait_gives_up_and_skips_the_item(monkeypatch):
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_batch_wait_gives_up_and_skips_the_item(monkeypatch, noalloc):
     """One kernel with per-shell dependencies (split 0), forward, out of place:
     with every wait made unreachable, every phi item gives up, so each output
     is the theta pass alone (bitwise what a plan's theta pass gives) and the
@@ -82,15 +84,18 @@ def test_batch_wait_gives_up_and_skips_the_item(monkeypatch):
         plan.close()
     monkeypatch.setenv("SPHFILT_FAULT", "wait")
     outs = [torch.full_like(x, np.nan) for x in xs]
-    with pytest.raises(_lib.SphfiltError):
-        batch.apply(xs, outs, check=True)
+    if noalloc:
+        batch.apply_noalloc(xs, outs)
+    else:
+        with pytest.raises(_lib.SphfiltError):
+            batch.apply(xs, outs, check=True)
     torch.cuda.synchronize()
     assert batch.status() == 1
     for o, t in zip(outs, theta_only):
         assert torch.equal(o.cpu(), t)
     monkeypatch.delenv("SPHFILT_FAULT")
     outs = [torch.full_like(x, np.nan) for x in xs]
-    batch.apply(xs, outs)
+    (batch.apply_noalloc if noalloc else batch.apply)(xs, outs)
     torch.cuda.synchronize()
     assert batch.status() == 0
     for o, f in zip(outs, full):
