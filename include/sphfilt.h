@@ -1,7 +1,7 @@
 /*
  * sphfilt.h -- C-ABI of the double FFT filter for spherical grids on MI355X.
  *
- * The operation (arXiv:2305.01537, Sec. II.B "Filtering algorithms"):
+ * The operation (arXiv:2305.01537, Sec. II.A "Filtering algorithms"):
  *
  *   Every evolved field X(x1, theta, phi) is filtered first along theta, then
  *   along phi.
@@ -53,18 +53,18 @@ extern "C" {
 #define SPHFILT_EDEVICE      (-3)  /* HIP runtime or kernel launch error          */
 #define SPHFILT_EUNSUPPORTED (-4)  /* valid for the method, not built here (size) */
 
-/* ---- filter kinds (Sec. II.B) ----------------------------------------- */
+/* ---- filter kinds (Sec. II.A) ----------------------------------------- */
 #define SPHFILT_EXP   0   /* f = 1 for |l| <= c, exp(-(|l| - c)) above        (eq. exp_filter)      */
 #define SPHFILT_GAUSS 1   /* f = exp(log(0.9) (|l| / (c + 1))^2)               (eq. gaussian_filter) */
 #define SPHFILT_SHARP 2   /* f = 1 for |l| <= c, 0 above (sharp low-pass named beside eq. exp_filter) */
 #define SPHFILT_HYBRID 3  /* per line: GAUSS if Jameson's detector fires, else EXP (the automatic
-                             switch at the end of Sec. II.B); see sphfilt_cutoff and sphfilt_apply_ex */
+                             switch at the end of Sec. II.A); see sphfilt_cutoff and sphfilt_apply_ex */
 
 typedef struct sphfilt_plan_s  *sphfilt_plan;   /* opaque; immutable after create */
 typedef struct sphfilt_batch_s *sphfilt_batch;  /* opaque; see sphfilt_batch_create */
 
 /*
- * Cutoff parameters (Sec. II.B, l_max / m_max equations).
+ * Cutoff parameters (Sec. II.A, l_max / m_max equations).
  *   rho          [n_r] r_i / dr_min, each finite and > 0 (r is the physical
  *                radius, e.g. after a fisheye map).  NULL => uniform
  *                cell-centred grid rho_i = i + 1/2.
@@ -122,7 +122,7 @@ typedef struct {
  * Create a plan for n_fields fields on an n_r x n_theta x n_phi grid.
  *   out     receives the plan handle (set to NULL on error).
  *   parity  [n_fields] axis parity sign (-1)^a of each field, +1 or -1
- *           (Sec. II.B, the extension equation).
+ *           (Sec. II.A, the extension equation).
  *   cut     cutoff parameters, see sphfilt_cutoff.
  * Builds the cutoff tables, the lists of non-identity lines and the twiddle
  * tables on the host, then allocates and uploads them to the current HIP
@@ -143,7 +143,7 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
 int sphfilt_plan_destroy(sphfilt_plan plan);
 
 /*
- * out = Phi(Theta(in)): the double FFT filter, theta first (Sec. II.B).
+ * out = Phi(Theta(in)): the double FFT filter, theta first (Sec. II.A).
  *   in, out  device pointers to n_fields*n_r*n_theta*n_phi doubles, layout
  *            [f][r][theta][phi], each 16-byte aligned (hipMalloc and the
  *            PyTorch allocator give 256-byte alignment; the theta pass moves
@@ -177,11 +177,11 @@ int sphfilt_apply_adjoint(sphfilt_plan plan, const double *in, double *out, void
 int sphfilt_apply_ex(sphfilt_plan plan, const double *in, double *out, int adjoint,
                      unsigned char *theta_dec, unsigned char *phi_dec, int replay, void *stream);
 
-/* The theta-pass alone (Sec. II.B, theta FFT filter on extended lines).
+/* The theta-pass alone (Sec. II.A, theta FFT filter on extended lines).
  * Arguments and errors as for sphfilt_apply. */
 int sphfilt_apply_theta(sphfilt_plan plan, const double *in, double *out, void *stream);
 
-/* The phi-pass alone (Sec. II.B, phi FFT filter on rings). */
+/* The phi-pass alone (Sec. II.A, phi FFT filter on rings). */
 int sphfilt_apply_phi(sphfilt_plan plan, const double *in, double *out, void *stream);
 
 /* Work and traffic figures of a plan (host only, no device call). */
@@ -265,7 +265,7 @@ int sphfilt_plan_get_overlap(sphfilt_plan plan, int *mode);
  * hybrid fields, equal to rounding otherwise); the batch schedules every
  * patch's theta groups and ring-pair groups as items of one persistent
  * kernel, replayed from a captured HIP graph.  This is the GPU counterpart of
- * the paper's OpenMP loop over many line transforms on one rank (Sec. II.C).
+ * the paper's OpenMP loop over many line transforms on one rank (Sec. II.B).
  * ====================================================================== */
 
 /* One patch: grid, fields, parities and cutoffs, as for sphfilt_plan_create. */

@@ -2,7 +2,7 @@
 
 Arrays are numpy float64, C order, shape (n_fields, n_r, n_theta, n_phi).
 The per-field parameters follow the paper's filter (arXiv:2305.01537,
-Sec. II.B): parity sign (-1)^a, rho = r/dr_min per shell, the cutoff scale
+Sec. II.A): parity sign (-1)^a, rho = r/dr_min per shell, the cutoff scale
 cal-L per field and the filter kind per field.
 """
 import ctypes

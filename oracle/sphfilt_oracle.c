@@ -2,14 +2,14 @@
  * sphfilt_oracle.c -- TEST INFRASTRUCTURE ONLY.
  *
  * A plain, slow, obviously correct CPU definition of the double FFT filter
- * (arXiv:2305.01537, Sec. II.B "Filtering algorithms").  It exists so that the
+ * (arXiv:2305.01537, Sec. II.A "Filtering algorithms").  It exists so that the
  * GPU library can be checked against something written straight from the
  * paper.  Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark may load it; the product library never links or calls it, and it
  * shares no source with the GPU path.
  *
  * What it computes, in the paper's order and notation:
- *   Theta-pass (Sec. II.B, extension equation and the theta FFT filter):
+ *   Theta-pass (Sec. II.A, extension equation and the theta FFT filter):
  *     for every field f, shell i and meridian k < n_phi/2 build the
  *     2pi-periodic line  g(vartheta) = X(theta, phi_k)            on [0, pi]
  *                                     = (-1)^a X(2pi - vartheta, phi_k + pi) on [pi, 2pi],
@@ -20,13 +20,13 @@
  *   Forward filter = phi-pass after theta-pass (the paper filters in theta
  *   first, then in phi).  Adjoint = theta-pass after phi-pass, because each
  *   pass is a real symmetric operator.
- *   Cutoffs (Sec. II.B, the l_max / m_max equations):
+ *   Cutoffs (Sec. II.A, the l_max / m_max equations):
  *     l_max = max(floor, 2 rho L),  m_max = max(floor, 2 rho sin(theta_j) L),
  *     with rho = r / dr_min and floor = 2 in the paper.
  *   Masks: exponential filter (eq. exp_filter), Gaussian filter
  *     (eq. gaussian_filter) and the spectrally sharp low-pass the paper
  *     mentions beside them.
- *   Hybrid filter (the automatic switch at the end of Sec. II.B): for each
+ *   Hybrid filter (the automatic switch at the end of Sec. II.A): for each
  *     extended theta line and each phi ring of a field, Jameson's shock
  *     detector sigma_i = |u_{i-1} - 2 u_i + u_{i+1}| /
  *     (|u_{i-1}| + 2|u_i| + |u_{i+1}| + eps) is evaluated at every cell

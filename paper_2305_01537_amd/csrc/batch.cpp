@@ -3,7 +3,7 @@
 // schedule picked by an autotuner and remembered in a JSON cache.
 //
 // The operation per patch is exactly the plan's (arXiv:2305.01537,
-// Sec. II.B): theta-pass then phi-pass (forward), or the reverse (adjoint).
+// Sec. II.A): theta-pass then phi-pass (forward), or the reverse (adjoint).
 // What the batch adds is scheduling: every patch's theta groups and ring-pair
 // groups become items of one work list (see batch_kernels.h), so small patches do
 // not leave the GPU idle and one graph launch covers all of them.

@@ -1,6 +1,6 @@
 // host_tables.cpp -- host-side tables shared by plans and batches:
 // validation, the per-shell / per-ring-pair item lists with their cutoffs
-// (arXiv:2305.01537, Sec. II.B, the l_max / m_max equations), twiddles and
+// (arXiv:2305.01537, Sec. II.A, the l_max / m_max equations), twiddles and
 // the e^{-k} table of the exponential mask.
 #include "host_tables.h"
 

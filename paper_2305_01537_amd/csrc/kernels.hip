@@ -1,7 +1,7 @@
 // kernels.hip -- the fused shell kernel of the per-plan path and the launch
 // shapes of the pass kernels (the theta and phi kernels are in
 // kernels_theta.hip and kernels_phi.hip), double FFT filter (arXiv:2305.01537,
-// Sec. II.B) for gfx950, FP64.
+// Sec. II.A) for gfx950, FP64.
 // The work of a workgroup is done by the workers in line_filter.h, which the
 // batched persistent kernel (batch.hip) shares: the same arithmetic per line
 // (bit for bit where the compiler contracts multiply-adds the same way in

@@ -1,5 +1,5 @@
 // kernels_theta.hip -- per-plan theta-pass kernels
-// of the double FFT filter (arXiv:2305.01537, Sec. II.B) for gfx950, FP64: one
+// of the double FFT filter (arXiv:2305.01537, Sec. II.A) for gfx950, FP64: one
 // launch per pass over a plan's item list.  The work of a workgroup is done by
 // the workers in line_filter.h, which the batched kernel shares.
 #include "line_filter.h"

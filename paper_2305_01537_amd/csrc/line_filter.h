@@ -3,7 +3,7 @@
 // persistent kernel (device side).
 //
 // Both passes filter independent real lines of length N: FFT, multiply mode q
-// by f(|q|, cutoff), inverse FFT (arXiv:2305.01537, Sec. II.B).  Two real lines
+// by f(|q|, cutoff), inverse FFT (arXiv:2305.01537, Sec. II.A).  Two real lines
 // that share one cutoff are packed as the real and imaginary part of one
 // complex line; because the mask is real and even in q, the real and
 // imaginary parts of the result are the two filtered lines.

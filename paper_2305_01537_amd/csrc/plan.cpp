@@ -2,9 +2,9 @@
 //
 // A plan turns the filter's parameters into device tables once:
 //   * one item per shell (field, radius) for the theta-pass, carrying
-//     l_max = max(floor, 2 rho L) (Sec. II.B, l_max equation);
+//     l_max = max(floor, 2 rho L) (Sec. II.A, l_max equation);
 //   * one item per ring pair (j, n_theta-1-j) for the phi-pass, carrying
-//     m_max = max(floor, 2 rho sin(theta_j) L) (Sec. II.B, m_max equation);
+//     m_max = max(floor, 2 rho sin(theta_j) L) (Sec. II.A, m_max equation);
 //   * twiddle tables exp(-2 pi i j / N) for both line lengths.
 // Items whose mask is 1 on every mode (cutoff >= N/2 for the exponential and
 // sharp filters) are sorted after the others: an in-place call launches over

@@ -31,7 +31,7 @@ struct PhiItem {
 };
 
 // Hybrid-filter arguments of a pass (the automatic exponential/Gaussian
-// switch of Sec. II.B).  dec: one byte per real line, 1 = Gaussian; with
+// switch of Sec. II.A).  dec: one byte per real line, 1 = Gaussian; with
 // replay the decisions are read from it, otherwise they are detected and,
 // if dec is not null, recorded.  present: the launch has hybrid lines.
 struct HybridArgs {

@@ -5,7 +5,7 @@ checks tensor shapes and dtypes, passes raw device pointers and the current
 HIP stream through the C-ABI, and raises on a non-zero status.  PyTorch
 provides device memory and streams.
 
-The operator (arXiv:2305.01537, Sec. II.B): theta-filter on lines extended
+The operator (arXiv:2305.01537, Sec. II.A): theta-filter on lines extended
 across the poles, then phi-filter on rings, with cutoffs l_max = max(2, 2 rho L)
 and m_max = max(2, 2 rho sin(theta) L).  Its transpose is the phi-pass
 followed by the theta-pass; SphFilter uses it as the backward.

@@ -3,7 +3,7 @@
 This module only draws inputs; it contains none of the filter's arithmetic, so
 both the GPU library's tests and the CPU oracle's tests take their inputs from
 here.  Fields stand in for the evolved spacetime / GRMHD variables that the
-paper filters (arXiv:2305.01537, Sec. II.B): smooth sums of real spherical
+paper filters (arXiv:2305.01537, Sec. II.A): smooth sums of real spherical
 harmonics with a radial profile, plus white noise, with each field carrying an
 axis parity sign (+1 scalars, +-1 vector/tensor components).
 

@@ -106,7 +106,7 @@ def test_calls_reject_null_plan(L):
 
 # ---------------------------------------------------------------------------
 # Work figures: active lines recomputed here from the cutoff definitions
-# (Sec. II.B l_max / m_max equations; a line is the identity when its cutoff
+# (Sec. II.A l_max / m_max equations; a line is the identity when its cutoff
 # reaches the Nyquist mode N/2 for the exponential and sharp filters).
 # ---------------------------------------------------------------------------
 def expected_counts(n_fields, n_r, n_theta, n_phi, L, kind=0, floor=2.0):

@@ -8,7 +8,7 @@ mistake anywhere in the oracle -- a dropped sign, the wrong reversal index, the
 passes in the wrong order, a transposed operand, an off-by-one cutoff -- fails
 at least one of them.
 
-Paper: arXiv:2305.01537, Sec. II.B (extension equation, theta and phi FFT
+Paper: arXiv:2305.01537, Sec. II.A (extension equation, theta and phi FFT
 filters, l_max / m_max, eq. exp_filter, eq. gaussian_filter).
 """
 import json
@@ -475,7 +475,7 @@ def test_p10_library_fft_matches_grmhd_slice(oracle_mod):
 
 
 # --------------------------------------------------------------------------
-# Hybrid filter (the automatic switch at the end of Sec. II.B): Jameson's
+# Hybrid filter (the automatic switch at the end of Sec. II.A): Jameson's
 # detector picks the Gaussian filter for a line with a discontinuity and the
 # exponential filter otherwise.
 # --------------------------------------------------------------------------
