@@ -82,8 +82,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # the GPU takes ~10 ms of continuous work to reach its steady clock after
-    # the workload is generated on the host: 100 warm-up steps (~20 ms)
+    # every timed loop is preceded by >= 30 ms of the same call on the GPU
+    # (clock_warmup), whatever --warmup says
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--L", type=float, default=3.0, help="cutoff scale cal-L of every field")
@@ -103,14 +103,41 @@ def parse():
     ap.add_argument("--mixed-radix-only", action="store_true",
                     help="time only the 96 x 192 and 80 x 160 grids (lines with a radix-3 or "
                          "radix-5 stage)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=6.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
 
 
-def time_loop(torch, fn, bufs, steps, warmup, stream):
-    """Run fn(buf) `warmup` times untimed, then `steps` times between HIP events
-    recorded on `stream` (the stream the library launches on)."""
+# GPU time of the same call run before every timed loop, whatever --warmup
+# says: after host-side work the GPU takes ~10 ms of continuous load to reach
+# its steady clock, and a loop timed from a cold start reads ~10 % slow.
+CLOCK_WARMUP_MS = 30.0
+
+
+def clock_warmup(torch, fn, bufs, stream, min_ms=CLOCK_WARMUP_MS):
+    """Run fn in groups of 8 calls until the GPU has spent at least min_ms on
+    them (HIP events on `stream`); returns the GPU time spent."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    spent, k = 0.0, 0
+    while spent < min_ms and k < 100000:
+        e0.record(stream)
+        for _ in range(8):
+            fn(bufs[k % len(bufs)])
+            k += 1
+        e1.record(stream)
+        e1.synchronize()
+        spent += e0.elapsed_time(e1)
+    return spent
+
+
+def time_loop(torch, fn, bufs, steps, warmup, stream, info=None):
+    """Warm the clock (clock_warmup), run fn(buf) `warmup` times untimed, then
+    `steps` times between HIP events recorded on `stream` (the stream the
+    library launches on).  info, if given, receives the warm-up GPU time."""
+    warm = clock_warmup(torch, fn, bufs, stream)
+    if info is not None:
+        info["clock_warmup_ms"] = warm
     for k in range(warmup):
         fn(bufs[k % len(bufs)])
     torch.cuda.synchronize()
@@ -124,11 +151,28 @@ def time_loop(torch, fn, bufs, steps, warmup, stream):
     return t0.elapsed_time(t1) / steps      # ms per call
 
 
+def _median_rate(fn, points, reps):
+    """Median over `reps` runs of points / wall time of fn()."""
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    ts.sort()
+    return points / ts[len(ts) // 2], ts[len(ts) // 2]
+
+
 def cpu_baseline(w, L, budget_s):
-    """The oracle as it stands, timed on whole shells of the same workload:
-    one shell first to size the sample, then that many shells (field-major)."""
+    """The oracle as it stands (direct DFTs, OpenMP over lines), timed on this
+    host's cores.  `value`: the forward filter on whole shells of the share
+    workload (one shell first to size the sample, then that many shells,
+    field-major).  `legs`: the same oracle on the small and grmhd workloads,
+    whole, forward and adjoint, median of 3 runs; the adjoint on the share
+    sample; one thread on the small workload (whole) and on one field of the
+    grmhd workload and of the share."""
     import numpy as np
     import oracle
+    from paper_2305_01537_amd import synth
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     F, R = w.shape[0], w.shape[1]
     t = time.perf_counter()
@@ -138,27 +182,51 @@ def cpu_baseline(w, L, budget_s):
     n_f = max(1, n_sh // R) if n_sh >= R else 1
     n_r = R if n_sh >= R else n_sh
     sub = np.ascontiguousarray(w.x[:n_f, :n_r])
+    kw = dict(parity=w.parity[:n_f], rho=w.rho[:n_r], L=L)
     t = time.perf_counter()
-    oracle.forward(sub, parity=w.parity[:n_f], rho=w.rho[:n_r], L=L)
+    oracle.forward(sub, **kw)
     dt = time.perf_counter() - t
-    # one thread, on evenly spaced shells of field 0 (the same radial mix of
-    # theta-filtered and theta-idle shells; about budget/4 seconds)
+    t = time.perf_counter()
+    oracle.adjoint(sub, **kw)
+    dt_adj = time.perf_counter() - t
+    legs = {"share_sample_adjoint": {"value": sub.size / dt_adj, "seconds": dt_adj}}
+    singles = {}
+    for name in ("small", "grmhd"):
+        v = synth.workload(name)
+        kw_v = dict(parity=v.parity, rho=v.rho, L=v.L)
+        fwd, tf = _median_rate(lambda: oracle.forward(v.x, **kw_v), v.x.size, 3)
+        adj, ta = _median_rate(lambda: oracle.adjoint(v.x, **kw_v), v.x.size, 3)
+        legs[name] = {"shape": list(v.shape), "forward": fwd, "adjoint": adj,
+                      "forward_s": tf, "adjoint_s": ta, "runs": 3, "stat": "median"}
+    # one thread: the small workload whole, one field of grmhd, evenly spaced
+    # shells of one field of the share (the same radial mix of theta-filtered
+    # and theta-idle shells)
     prev = oracle.set_threads(1)
+    v = synth.workload("small")
+    singles["small"], _ = _median_rate(
+        lambda: oracle.forward(v.x, parity=v.parity, rho=v.rho, L=v.L), v.x.size, 3)
+    g = synth.workload("grmhd")
+    g1 = np.ascontiguousarray(g.x[:1])
+    singles["grmhd_field0"], _ = _median_rate(
+        lambda: oracle.forward(g1, parity=g.parity[:1], rho=g.rho, L=g.L[:1]), g1.size, 1)
     n1 = int(max(1, min(R, budget_s / 4 / max(one * threads, 1e-6))))
     idx = np.unique(np.linspace(0, R - 1, n1).round().astype(int))
     sub1 = np.ascontiguousarray(w.x[:1, idx])
     t = time.perf_counter()
     oracle.forward(sub1, parity=w.parity[:1], rho=w.rho[idx], L=L)
     dt1 = time.perf_counter() - t
+    singles["share_sample"] = sub1.size / dt1
     oracle.set_threads(prev)
     return {"value": sub.size / dt, "unit": "field-points/s", "cores": threads, "kind": "oracle",
             "sample": f"fields 0..{n_f - 1} x shells 0..{n_r - 1} of the share workload "
                       f"({sub.size} points, cal-L={L}), forward filter (theta then phi, "
                       f"direct DFTs), {dt:.1f} s",
             "host_cpu": host_cpu(),
-            "single_thread": {"value": sub1.size / dt1, "unit": "field-points/s",
-                              "sample": f"field 0 x {len(idx)} evenly spaced shells "
-                                        f"({sub1.size} points), {dt1:.1f} s"}}
+            "legs": legs,
+            "single_thread": {"unit": "field-points/s", "forward": singles,
+                              "sample": f"small: whole (median of 3); grmhd: field 0 "
+                                        f"({g1.size} points); share: field 0 x {len(idx)} "
+                                        f"evenly spaced shells ({sub1.size} points, {dt1:.1f} s)"}}
 
 
 def host_cpu():
@@ -385,6 +453,20 @@ def bench_short_lines(torch, steps, stream):
                         "fused_forward_ms": ms_f, "fused_GBps": 16 * pts / (ms_f * 1e-3) / 1e9,
                         "two_pass_forward_ms": ms_2,
                         "fused_points_per_s": pts / (ms_f * 1e-3)}
+        if N in (32, 64):
+            # the theta pass as the circulant product on the matrix cores:
+            # alone (two-pass path) and inside the fused shell kernel
+            from paper_2305_01537_amd.filter import THETA_MFMA
+            plan.set_theta_variant(THETA_MFMA)
+            ms_mt = time_loop(torch, lambda b: plan.apply_theta(b, out=b), bufs, steps, 2, stream)
+            ms_m2 = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 2, stream)
+            plan.set_fused(True)
+            ms_mf = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 2, stream)
+            out[f"N{N}"]["mfma"] = {
+                "theta_GBps": 16 * pts / (ms_mt * 1e-3) / 1e9, "theta_ms": ms_mt,
+                "two_pass_forward_ms": ms_m2, "fused_forward_ms": ms_mf,
+                "fused_GBps": 16 * pts / (ms_mf * 1e-3) / 1e9,
+                "fft_theta_ms": ms_t}
         plan.close()
         del bufs, x0
         torch.cuda.empty_cache()
@@ -431,7 +513,9 @@ def main():
     log(f"workload ready in {time.perf_counter() - t_start:.1f} s; stats {st}")
 
     # ---- the timed region: K forward filters, in place -------------------
-    ms_fwd = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, args.steps, args.warmup, stream)
+    warm_info = {}
+    ms_fwd = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, args.steps, args.warmup, stream,
+                       info=warm_info)
     log(f"forward {ms_fwd:.4f} ms/step")
     points = st["n_points"]
     value = points / (ms_fwd * 1e-3)
@@ -550,6 +634,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "clock_warmup_ms": warm_info["clock_warmup_ms"],
         "ms_per_step": ms_fwd,
         "higher_is_better": True,
         "scaling": "weak",

@@ -235,6 +235,50 @@ int sphfilt_plan_set_fused(sphfilt_plan plan, int enable);
 int sphfilt_plan_get_fused(sphfilt_plan plan, int *enable, int *shells_fused);
 
 /*
+ * Autotune a plan: the theta tile width and phi ring pairs per workgroup
+ * (sphfilt_plan_set_schedule), fused shells, the theta variant and the
+ * overlap mode, by coordinate descent from the plan's current settings, each
+ * candidate timed as a forward filter in place on scratch fields of the
+ * plan's size that the call allocates and frees.  The untuned settings are a
+ * candidate, so the pick is never slower than them by the tuner's own
+ * measurement.
+ *   tune_cache_path  a JSON file shared with the batch tuner: if it holds
+ *                    settings for this plan (grid, fields, cutoffs) on this
+ *                    GPU architecture they are applied without timing, else
+ *                    the tuner runs and records its pick there (SPHFILT_EINVAL
+ *                    if the file cannot be written).  NULL: the file named
+ *                    by SPHFILT_TUNE_CACHE if set and not empty, else tune
+ *                    without recording.
+ * Synchronous; not thread-safe against concurrent calls on the same plan.
+ * sphfilt_plan_tuned_times reports the tuner's time of one forward call with
+ * the pick and with the settings it started from (negative when not tuned;
+ * NULL outputs are skipped).
+ */
+int sphfilt_plan_tune(sphfilt_plan plan, const char *tune_cache_path);
+int sphfilt_plan_tuned_times(sphfilt_plan plan, double *tuned_us, double *default_us);
+
+/*
+ * Theta-pass variant (grids with n_phi = 2 * n_theta in {32, 64} only).
+ * On one extended theta line the theta filter is the circular convolution
+ * with c[d] = (1/N) sum_q f(|q|; l_max) cos(2 pi q d / N), the inverse
+ * transform of the mask (Sec. II.A, theta filter); all lines of a shell share
+ * l_max, so a shell's theta pass is one product of that N x N circulant with
+ * the N x N/2 matrix of its extended lines.  SPHFILT_THETA_MFMA computes it
+ * that way on the FP64 matrix cores (2N flops per point instead of the
+ * FFT's ~5 log2 N, no transposes), in the two-pass path and inside the fused
+ * shell kernel; hybrid fields keep the FFT.  Results equal the FFT path's to
+ * rounding (a different summation order), not bit for bit.
+ *   variant  SPHFILT_THETA_FFT (the default) or SPHFILT_THETA_MFMA.
+ * set returns SPHFILT_EINVAL for other values and SPHFILT_EUNSUPPORTED for
+ * MFMA on other grids; not thread-safe against concurrent apply calls on
+ * the same plan.
+ */
+#define SPHFILT_THETA_FFT  0
+#define SPHFILT_THETA_MFMA 1
+int sphfilt_plan_set_theta_variant(sphfilt_plan plan, int variant);
+int sphfilt_plan_get_theta_variant(sphfilt_plan plan, int *variant);
+
+/*
  * Overlapped passes (in place, shells not fused).  The rings of shells whose
  * theta mask is all ones do not depend on the theta pass.  An overlapped
  * in-place call runs them on a second stream owned by the plan, alongside the
@@ -283,13 +327,14 @@ typedef struct {
  *                    192 points) runs a kernel instance that carries those
  *                    lengths too (one wave per SIMD).  Read during the call
  *                    only.
- *   tune_cache_path  NULL: use the default schedule (no tuning).  Otherwise
- *                    a JSON file: if it holds a schedule for this set of
+ *   tune_cache_path  a JSON file: if it holds a schedule for this set of
  *                    patches on this GPU architecture, that schedule is used;
- *                    if not, the autotuner times the candidate schedules on
- *                    scratch fields it allocates and frees, and records the
- *                    winner there (SPHFILT_EINVAL if the file cannot be
- *                    written).
+ *                    if not, the autotuner times the candidate schedules (see
+ *                    sphfilt_batch_schedule) on scratch fields it allocates
+ *                    and frees, and records the winner there (SPHFILT_EINVAL
+ *                    if the file cannot be written).  NULL: the file named by
+ *                    the environment variable SPHFILT_TUNE_CACHE if it is set
+ *                    and not empty, else the untuned default schedule.
  * The batch owns its device tables and a small set of work counters; calls on
  * one batch must be stream-ordered (two overlapping calls on one batch race
  * on the counters).
@@ -369,6 +414,40 @@ int sphfilt_batch_tune(sphfilt_batch batch, const char *tune_cache_path);
 int sphfilt_batch_set_schedule(sphfilt_batch batch, int split, int workgroups_per_cu);
 int sphfilt_batch_get_schedule(sphfilt_batch batch, int *split, int *workgroups_per_cu,
                                double *tuned_us);
+
+/*
+ * The whole schedule of a batch, as the autotuner searches it (coordinate
+ * descent from the untuned schedule, every candidate timed on scratch fields
+ * with the batch's own kernels; the pick and both times are recorded in the
+ * JSON cache):
+ *   split, workgroups_per_cu  as for sphfilt_batch_set_schedule (get: the
+ *                      effective workgroups per CU).
+ *   fused              fused items (see sphfilt_batch_set_fused), 0 or 1.
+ *   theta_tiles        meridian tiles per theta work item: 1, 2, 4 or 8 (an
+ *                      item runs them one after another).
+ *   phi_groups         workgroup rounds of ring pairs per phi work item: 1,
+ *                      2, 4 or 8.
+ *   theta_cols[i]      theta sub-tile width (as theta_cols of
+ *                      sphfilt_plan_set_schedule) for patches whose theta
+ *                      line has {32, 48, 64, 80, 96, 128, 160, 192, 256}[i]
+ *                      points; 0 = the default width.  A width a patch's grid
+ *                      does not take falls back to its default.
+ *   tuned_us, default_us  (get only) the tuner's time of one call with the
+ *                      picked and with the untuned schedule; negative when
+ *                      not tuned.
+ * set_schedule_ex returns SPHFILT_EINVAL for values outside these sets;
+ * changing the item shapes (everything but split and workgroups_per_cu)
+ * synchronises the device and rebuilds the work lists and graphs.  Results
+ * do not depend on the schedule except through theta_cols where a theta line
+ * has 256 points (round-off only; see sphfilt_plan_set_schedule).
+ */
+typedef struct {
+    int split, workgroups_per_cu, fused, theta_tiles, phi_groups;
+    int theta_cols[9];
+    double tuned_us, default_us;
+} sphfilt_batch_schedule;
+int sphfilt_batch_set_schedule_ex(sphfilt_batch batch, const sphfilt_batch_schedule *sched);
+int sphfilt_batch_get_schedule_ex(sphfilt_batch batch, sphfilt_batch_schedule *sched);
 
 /* Device error word of the batch's last call (synchronises the device): 0,
  * or 1 if a second-pass item gave up waiting for its shells (a library bug;

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libsphfilt.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 EXP, GAUSS, SHARP, HYBRID = 0, 1, 2, 3
+THETA_FFT, THETA_MFMA = 0, 1
 
 c_int_p = ctypes.POINTER(ctypes.c_int)
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -31,6 +32,16 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class BatchSchedule(ctypes.Structure):
+    _fields_ = [("split", ctypes.c_int), ("workgroups_per_cu", ctypes.c_int), ("fused", ctypes.c_int),
+                ("theta_tiles", ctypes.c_int), ("phi_groups", ctypes.c_int),
+                ("theta_cols", ctypes.c_int * 9), ("tuned_us", ctypes.c_double),
+                ("default_us", ctypes.c_double)]
+
+
+THETA_LINES = (32, 48, 64, 80, 96, 128, 160, 192, 256)
 
 
 class PatchDesc(ctypes.Structure):
@@ -56,6 +67,10 @@ SIGNATURES = {
     "sphfilt_plan_get_schedule": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
     "sphfilt_plan_set_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sphfilt_plan_get_fused": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
+    "sphfilt_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "sphfilt_plan_tuned_times": (ctypes.c_int, [ctypes.c_void_p, c_double_p, c_double_p]),
+    "sphfilt_plan_set_theta_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sphfilt_plan_get_theta_variant": (ctypes.c_int, [ctypes.c_void_p, c_int_p]),
     "sphfilt_plan_set_overlap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sphfilt_plan_get_overlap": (ctypes.c_int, [ctypes.c_void_p, c_int_p]),
     "sphfilt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
@@ -69,6 +84,8 @@ SIGNATURES = {
     "sphfilt_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "sphfilt_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "sphfilt_batch_get_schedule": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_double_p]),
+    "sphfilt_batch_set_schedule_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchSchedule)]),
+    "sphfilt_batch_get_schedule_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchSchedule)]),
     "sphfilt_batch_status": (ctypes.c_int, [ctypes.c_void_p, c_int_p]),
     "sphfilt_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "sphfilt_batch_set_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),

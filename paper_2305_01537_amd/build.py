@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "sphfilt")
 LIB = os.path.join(HERE, "libsphfilt.so")
-SOURCES = ["host_tables.cpp", "plan.cpp", "batch.cpp", "kernels.hip", "kernels_theta.hip",
+SOURCES = ["host_tables.cpp", "tune_cache.cpp", "plan.cpp", "batch.cpp", "kernels.hip", "kernels_theta.hip",
            "kernels_phi.hip", "batch.hip", "batch_plain.hip", "batch_hybrid.hip",
            "batch_mixed.hip", "batch_mixed_hybrid.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

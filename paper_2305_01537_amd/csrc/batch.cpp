@@ -10,6 +10,7 @@
 #include "../../include/sphfilt.h"
 #include "batch_internal.h"
 #include "host_tables.h"
+#include "tune_cache.h"
 
 #include <hip/hip_runtime.h>
 
@@ -99,9 +100,14 @@ struct sphfilt_batch_s {
     ModeWork modes[4];
     std::vector<GraphEntry> graphs;
     int split = 0, wpc = -1;           // schedule: see effective_wpc
+    int theta_tiles = 1;               // meridian tiles per theta item
+    int phi_groups = 1;                // workgroup rounds of ring pairs per phi item
+    std::map<int, int> theta_cols;     // theta line length -> sub-tile width (tuned; else default)
+    std::vector<BatchPatchDev> pdev;   // host copy of d_patches
     int hybrid = 0;                    // some patch has a hybrid field
     int variant = 0;                   // kernel instance: kBatchHybrid | kBatchMixedRadix
     double tuned_us = -1.0;
+    double default_us = -1.0;          // the untuned schedule's time, measured by the tuner
     uint64_t clock = 0;
     hipStream_t capture_stream = nullptr;
     hipStream_t side_stream = nullptr;    // parallel branch of split = 2 graphs
@@ -112,19 +118,12 @@ struct sphfilt_batch_s {
 
 namespace {
 
-uint64_t fnv(uint64_t h, const void *data, size_t n)
-{
-    const unsigned char *p = (const unsigned char *)data;
-    for (size_t i = 0; i < n; ++i) {
-        h ^= p[i];
-        h *= 1099511628211ULL;
-    }
-    return h;
-}
-
 uint64_t signature(const std::string &arch, int n_patches, const sphfilt_patch_desc *d)
 {
-    uint64_t h = 1469598103934665603ULL;
+    auto fnv = fnv1a;
+    uint64_t h = kFnvSeed;
+    const char tag[] = "batch";
+    h = fnv(h, tag, sizeof(tag));
     h = fnv(h, arch.data(), arch.size());
     h = fnv(h, &n_patches, sizeof(n_patches));
     for (int p = 0; p < n_patches; ++p) {
@@ -143,95 +142,31 @@ uint64_t signature(const std::string &arch, int n_patches, const sphfilt_patch_d
     return h;
 }
 
-std::string hex64(uint64_t v)
-{
-    char buf[17];
-    std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)v);
-    return buf;
-}
-
-
-// ---- the JSON tuning cache: one entry per line -------------------------
-//   {"sphfilt_tune_cache": 1, "entries": [
-//    {"sig": "<16 hex>", "arch": "gfx950", "split": 0, "wpc": 2, "fused": 1, "us": 812.5},
-//   ...]}
-bool cache_lookup(const char *path, const std::string &sig, int *split, int *wpc, int *fused)
-{
-    std::ifstream f(path);
-    if (!f) return false;
-    std::string line;
-    const std::string key = "\"sig\": \"" + sig + "\"";
-    while (std::getline(f, line)) {
-        if (line.find(key) == std::string::npos) continue;
-        const size_t a = line.find("\"split\": "), b = line.find("\"wpc\": ");
-        if (a == std::string::npos || b == std::string::npos) return false;
-        *split = std::atoi(line.c_str() + a + 9);
-        *wpc = std::atoi(line.c_str() + b + 7);
-        const size_t c = line.find("\"fused\": ");
-        *fused = c == std::string::npos ? 1 : std::atoi(line.c_str() + c + 9);
-        return *split >= 0 && *split <= 2 && *wpc >= -1 && *wpc <= 64 && (*fused == 0 || *fused == 1);
-    }
-    return false;
-}
-
-bool cache_store(const char *path, const std::string &sig, const std::string &arch, int split,
-                 int wpc, int fused, double us)
-{
-    std::vector<std::string> keep;
-    {
-        std::ifstream f(path);
-        std::string line;
-        while (f && std::getline(f, line)) {
-            if (line.find("\"sig\": \"") == std::string::npos) continue;
-            if (line.find("\"sig\": \"" + sig + "\"") != std::string::npos) continue;
-            while (!line.empty() && (line.back() == ',' || line.back() == ']' || line.back() == '}' ||
-                                     line.back() == ' '))
-                line.pop_back();
-            keep.push_back(line + "}");
-        }
-    }
-    std::ostringstream e;
-    e << "  {\"sig\": \"" << sig << "\", \"arch\": \"" << arch << "\", \"split\": " << split
-      << ", \"wpc\": " << wpc << ", \"fused\": " << fused << ", \"us\": " << us << "}";
-    keep.push_back(e.str());
-    const std::string tmp = std::string(path) + ".tmp";
-    {
-        std::ofstream o(tmp);
-        if (!o) return false;
-        o << "{\"sphfilt_tune_cache\": 1, \"entries\": [\n";
-        for (size_t i = 0; i < keep.size(); ++i) {
-            std::string l = keep[i];
-            if (l.rfind("  ", 0) != 0) l = "  " + l;
-            o << l << (i + 1 < keep.size() ? ",\n" : "\n");
-        }
-        o << "]}\n";
-        if (!o) return false;
-    }
-    return std::rename(tmp.c_str(), path) == 0;
-}
-
 // ---- work lists ----------------------------------------------------------
 void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
               std::vector<BatchWork> *work, std::vector<int> *shells)
 {
     const PatchHost &p = b->patches[(size_t)pi];
     if (theta) {
+        // groups of S shells; each item takes up to theta_tiles meridian tiles
         const int n = all ? (int)p.tables.theta.size() : p.tables.theta_active;
         const int C = theta_lines_per_group(2 * p.n_theta);
         const int S = C / p.cols;
         const int T = (p.n_phi / 2) / (2 * p.cols);
+        const int TI = std::max(1, std::min(b->theta_tiles, T));
         for (int g = 0; g * S < n; ++g) {
             const int nv = std::min(S, n - g * S);
             const int off = (int)shells->size();
             for (int u = 0; u < nv; ++u)
                 shells->push_back(p.shell_base + p.tables.theta[(size_t)(g * S + u)].shell);
-            for (int tile = 0; tile < T; ++tile)
+            for (int tile = 0; tile < T; tile += TI)
                 work->push_back(BatchWork{pi, 0, (int16_t)second, p.theta_off + g * S, (int16_t)nv,
-                                          (int16_t)tile, off, nv, 0, 0});
+                                          (int16_t)tile, off, nv, 0, std::min(TI, T - tile)});
         }
     } else {
+        // up to phi_groups workgroup rounds of L ring pairs per item
         const int n = all ? (int)p.tables.phi.size() : p.tables.phi_active;
-        const int L = default_phi_lines(p.n_phi);
+        const int L = default_phi_lines(p.n_phi) * std::max(1, b->phi_groups);
         for (int c = 0; c * L < n; ++c) {
             const int nv = std::min(L, n - c * L);
             std::vector<int> s;
@@ -242,7 +177,7 @@ void add_pass(const sphfilt_batch b, int pi, bool theta, bool all, bool second,
             const int off = (int)shells->size();
             shells->insert(shells->end(), s.begin(), s.end());
             work->push_back(BatchWork{pi, 1, (int16_t)second, p.phi_off + c * L, (int16_t)nv, 0, off,
-                                      (int)s.size(), 0, 0});
+                                      (int)s.size(), 0, 1});
         }
     }
 }
@@ -268,7 +203,7 @@ void add_fused_shells(const sphfilt_batch b, int pi, bool adjoint, std::vector<B
     for (int g = 0; g * S < p.tables.n_fused; ++g) {
         const int nv = std::min(S, p.tables.n_fused - g * S);
         work->push_back(BatchWork{pi, 2, 0, p.theta_off + g * S, (int16_t)nv, (int16_t)adjoint, 0, 0,
-                                  p.fc_off + g * S * lines, 0});
+                                  p.fc_off + g * S * lines, 1});
     }
 }
 
@@ -276,10 +211,10 @@ void add_rest_rings(const sphfilt_batch b, int pi, bool all, std::vector<BatchWo
 {
     const PatchHost &p = b->patches[(size_t)pi];
     const int n = all ? (int)p.tables.phi_rest.size() : p.tables.phi_rest_active;
-    const int L = default_phi_lines(p.n_phi);
+    const int L = default_phi_lines(p.n_phi) * std::max(1, b->phi_groups);
     for (int c = 0; c * L < n; ++c)
         work->push_back(BatchWork{pi, 1, 0, p.phi_rest_off + c * L, (int16_t)std::min(L, n - c * L), 0,
-                                  0, 0, 0, 0});
+                                  0, 0, 0, 1});
 }
 
 int build_mode(sphfilt_batch b, int mode)
@@ -580,6 +515,115 @@ int time_schedule(sphfilt_batch b, const std::vector<double *> &bufs, hipStream_
     return SPHFILT_OK;
 }
 
+// ---- schedules and the autotuner ----------------------------------------
+// The supported theta line lengths, the index order of
+// sphfilt_batch_schedule::theta_cols.
+constexpr int kLines[9] = {32, 48, 64, 80, 96, 128, 160, 192, 256};
+
+struct Sched {
+    int fused = 1, split = 0, wpc = -1, theta_tiles = 1, phi_groups = 1;
+    std::map<int, int> cols;      // theta line length -> sub-tile width (absent: default)
+};
+
+Sched current(const sphfilt_batch b)
+{
+    Sched c;
+    c.fused = b->fused;
+    c.split = b->split;
+    c.wpc = b->wpc;
+    c.theta_tiles = b->theta_tiles;
+    c.phi_groups = b->phi_groups;
+    c.cols = b->theta_cols;
+    return c;
+}
+
+// The theta sub-tile width of patch p under the batch's tile table: the
+// tuned width for its line length where the patch's grid takes it, else the
+// default.
+int patch_cols(const sphfilt_batch b, const PatchHost &p)
+{
+    auto it = b->theta_cols.find(2 * p.n_theta);
+    if (it != b->theta_cols.end() && theta_shape_ok(2 * p.n_theta, it->second, p.n_phi)) return it->second;
+    return default_theta_cols(2 * p.n_theta, p.n_phi);
+}
+
+// Make `c` the batch's schedule.  Work lists and graphs are dropped (and
+// rebuilt) when the item shapes change; the patch table is re-uploaded when a
+// tile width changes.  Synchronises the device in those cases.
+int set_sched(sphfilt_batch b, const Sched &c)
+{
+    const bool shapes = c.fused != b->fused || c.theta_tiles != b->theta_tiles ||
+                        c.phi_groups != b->phi_groups || c.cols != b->theta_cols;
+    b->split = c.split;
+    b->wpc = c.wpc;
+    if (!shapes) return SPHFILT_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return SPHFILT_EDEVICE;
+    free_work(b);
+    b->fused = c.fused;
+    b->theta_tiles = c.theta_tiles;
+    b->phi_groups = c.phi_groups;
+    b->theta_cols = c.cols;
+    bool changed = false;
+    for (size_t i = 0; i < b->patches.size(); ++i) {
+        PatchHost &p = b->patches[i];
+        const int cols = patch_cols(b, p);
+        if (cols != p.cols) {
+            p.cols = cols;
+            b->pdev[i].cp_log2 = ilog2_int(cols);
+            changed = true;
+        }
+    }
+    if (changed && hipMemcpy(b->d_patches, b->pdev.data(), sizeof(BatchPatchDev) * b->pdev.size(),
+                             hipMemcpyHostToDevice) != hipSuccess)
+        return SPHFILT_EDEVICE;
+    return ensure_modes(b);
+}
+
+TuneFields sched_fields(const sphfilt_batch b, const Sched &c, double us, double default_us)
+{
+    TuneFields f;
+    f["what"] = tune_str("batch");
+    f["arch"] = tune_str(b->arch);
+    f["split"] = tune_num(c.split);
+    f["wpc"] = tune_num(c.wpc);
+    f["fused"] = tune_num(c.fused);
+    f["theta_tiles"] = tune_num(c.theta_tiles);
+    f["phi_groups"] = tune_num(c.phi_groups);
+    std::string cols;
+    for (const auto &kv : c.cols) cols += (cols.empty() ? "" : ",") + std::to_string(kv.first) + ":" + std::to_string(kv.second);
+    f["theta_cols"] = tune_str(cols);
+    f["us"] = tune_num(us);
+    f["default_us"] = tune_num(default_us);
+    return f;
+}
+
+bool sched_from_fields(const sphfilt_batch b, const TuneFields &f, Sched *c, double *us, double *def)
+{
+    Sched r;
+    std::string what, cols;
+    if (!tune_string(f, "what", &what) || what != "batch" || !tune_int(f, "split", &r.split) ||
+        !tune_int(f, "wpc", &r.wpc) || !tune_int(f, "fused", &r.fused) ||
+        !tune_int(f, "theta_tiles", &r.theta_tiles) || !tune_int(f, "phi_groups", &r.phi_groups) ||
+        !tune_string(f, "theta_cols", &cols))
+        return false;
+    if (r.split < 0 || r.split > 2 || r.wpc < -1 || r.wpc > b->max_wpc || (r.fused != 0 && r.fused != 1) ||
+        r.theta_tiles < 1 || r.theta_tiles > 8 || r.phi_groups < 1 || r.phi_groups > 8)
+        return false;
+    std::istringstream in(cols);
+    std::string item;
+    while (std::getline(in, item, ',')) {
+        const size_t colon = item.find(':');
+        if (colon == std::string::npos) return false;
+        const int n = std::atoi(item.substr(0, colon).c_str()), w = std::atoi(item.c_str() + colon + 1);
+        if (!supported_line(n) || (w != 4 && w != 8 && w != 16 && w != 32 && w != 64)) return false;
+        r.cols[n] = w;
+    }
+    *c = r;
+    if (!tune_double(f, "us", us)) *us = -1.0;
+    if (!tune_double(f, "default_us", def)) *def = -1.0;
+    return true;
+}
+
 int tune(sphfilt_batch b, const char *cache_path)
 {
     long long total = 0;
@@ -598,33 +642,73 @@ int tune(sphfilt_batch b, const char *cache_path)
     if (hipMemset(scratch, 0, sizeof(double) * (size_t)total) != hipSuccess ||
         hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
         rc = SPHFILT_EDEVICE;
-    int best_split = 0, best_wpc = -1, best_fused = b->fused;
-    double best = 1e300;
-    // fused items only matter when some patch has them
+
+    // coordinate descent from the untuned schedule: (fused items, split,
+    // workgroups per CU), then the theta tile width of each line length, the
+    // tiles per theta item, the ring groups per phi item, then split and
+    // workgroups per CU again.  The untuned schedule is one of the candidates,
+    // so the pick is never slower than it by the tuner's own measurement.
+    const Sched start{};
+    Sched best = start;
+    double best_us = 1e300, default_us = -1.0;
+    auto try_sched = [&](const Sched &c) {
+        if (rc) return;
+        rc = set_sched(b, c);
+        double us = 0;
+        if (!rc) rc = time_schedule(b, bufs, s, 5, &us);
+        if (rc) return;
+        if (default_us < 0) default_us = us;          // the first candidate is `start`
+        if (us < best_us) {
+            best_us = us;
+            best = c;
+        }
+    };
+    try_sched(start);
     bool any_fused = false;
     for (const PatchHost &p : b->patches) any_fused |= p.tables.n_fused > 0 && p.tables.n_fused == p.tables.theta_active;
-    for (int fz = any_fused ? 1 : b->fused; fz >= (any_fused ? 0 : b->fused) && !rc; --fz) {
-        if (fz != b->fused) {
-            if (hipStreamSynchronize(s) != hipSuccess) { rc = SPHFILT_EDEVICE; break; }
-            free_work(b);
-            b->fused = fz;
-        }
-        for (int split = 0; split <= 2 && !rc; ++split) {
+    auto split_wpc = [&](int fused) {
+        for (int split = 0; split <= 2 && !rc; ++split)
             for (int wpc = -1; wpc <= b->max_wpc && !rc; ++wpc) {
                 if (wpc == 0) continue;
-                b->split = split;
-                b->wpc = wpc;
-                double us = 0;
-                rc = time_schedule(b, bufs, s, 5, &us);
-                if (!rc && us < best) {
-                    best = us;
-                    best_split = split;
-                    best_wpc = wpc;
-                    best_fused = fz;
-                }
+                Sched c = best;
+                c.fused = fused;
+                c.split = split;
+                c.wpc = wpc;
+                try_sched(c);
             }
+    };
+    for (int fz = 1; fz >= 0 && !rc; --fz)
+        if (fz == 1 || any_fused) split_wpc(fz);
+    // theta tile widths, per line length with two-pass theta work
+    for (int n : kLines) {
+        bool has = false;
+        for (const PatchHost &p : b->patches)
+            has |= 2 * p.n_theta == n && !(best.fused && p.tables.n_fused > 0 &&
+                                           p.tables.n_fused == p.tables.theta_active);
+        if (!has) continue;
+        const Sched base = best;
+        for (int w : {4, 8, 16, 32, 64}) {
+            bool valid = false;
+            for (const PatchHost &p : b->patches) valid |= 2 * p.n_theta == n && theta_shape_ok(n, w, p.n_phi);
+            if (!valid) continue;
+            Sched c = base;
+            c.cols[n] = w;
+            if (c.cols == best.cols) continue;
+            try_sched(c);
         }
     }
+    for (int t : {2, 4}) {
+        Sched c = best;
+        c.theta_tiles = t;
+        try_sched(c);
+    }
+    for (int g : {2, 4}) {
+        Sched c = best;
+        c.phi_groups = g;
+        try_sched(c);
+    }
+    split_wpc(best.fused);
+
     if (s) (void)hipStreamSynchronize(s);
     // drop the graphs that point at the scratch fields
     for (auto it = b->graphs.begin(); it != b->graphs.end();) {
@@ -638,17 +722,11 @@ int tune(sphfilt_batch b, const char *cache_path)
     if (s) (void)hipStreamDestroy(s);
     (void)hipFree(scratch);
     if (rc) return rc;
-    if (b->fused != best_fused) {
-        free_work(b);
-        b->fused = best_fused;
-    }
-    b->split = best_split;
-    b->wpc = best_wpc;
-    b->tuned_us = best;
-    rc = ensure_modes(b);
+    rc = set_sched(b, best);
     if (rc) return rc;
-    if (cache_path && !cache_store(cache_path, hex64(b->signature), b->arch, best_split, best_wpc,
-                                   best_fused, best))
+    b->tuned_us = best_us;
+    b->default_us = default_us;
+    if (cache_path && !tune_cache_put(cache_path, hex64(b->signature), sched_fields(b, best, best_us, default_us)))
         return SPHFILT_EINVAL;
     return SPHFILT_OK;
 }
@@ -745,6 +823,7 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
         if (!rc) rc = upload(&b->d_ph, all_ph);
         if (!rc) rc = upload(&b->d_fc, all_fc);
         if (!rc) rc = upload(&b->d_patches, pdev);
+        if (!rc) b->pdev = pdev;
         if (!rc) rc = upload(&b->d_eneg, exp_table());
         if (!rc) rc = upload(&b->d_counters, std::vector<int>((size_t)std::max(1, b->n_shells_total), 0));
         if (!rc) rc = upload(&b->d_tickets, std::vector<int>(3, 0));
@@ -759,14 +838,18 @@ int sphfilt_batch_create(sphfilt_batch *out, int n_patches, const sphfilt_patch_
     }
     (void)th;
     (void)ph;
-    if (!rc && tune_cache_path) {
-        int split = 0, wpc = 0, fused = 1;
-        if (cache_lookup(tune_cache_path, hex64(b->signature), &split, &wpc, &fused)) {
-            b->split = split;
-            b->wpc = wpc;
-            b->fused = fused;
+    // NULL: the cache named by $SPHFILT_TUNE_CACHE, if any
+    const char *cache = tune_cache_path ? tune_cache_path : tune_cache_default();
+    if (!rc && cache) {
+        TuneFields f;
+        Sched c;
+        double us = -1.0, def = -1.0;
+        if (tune_cache_get(cache, hex64(b->signature), &f) && sched_from_fields(b, f, &c, &us, &def)) {
+            rc = set_sched(b, c);
+            b->tuned_us = us;
+            b->default_us = def;
         } else {
-            rc = tune(b, tune_cache_path);
+            rc = tune(b, cache);
         }
     }
     // the work lists of every mode, and the device address of the static
@@ -840,6 +923,50 @@ int sphfilt_batch_get_schedule(sphfilt_batch batch, int *split, int *workgroups_
     if (split) *split = batch->split;
     if (workgroups_per_cu) *workgroups_per_cu = effective_wpc(batch, batch->wpc);
     if (tuned_us) *tuned_us = batch->tuned_us;
+    return SPHFILT_OK;
+}
+
+int sphfilt_batch_set_schedule_ex(sphfilt_batch batch, const sphfilt_batch_schedule *sched)
+{
+    if (!batch || !sched) return SPHFILT_EINVAL;
+    const sphfilt_batch_schedule &q = *sched;
+    auto pow2_le8 = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
+    if (q.split < 0 || q.split > 2 || q.workgroups_per_cu < -1 || q.workgroups_per_cu > batch->max_wpc ||
+        (q.fused != 0 && q.fused != 1) || !pow2_le8(q.theta_tiles) || !pow2_le8(q.phi_groups))
+        return SPHFILT_EINVAL;
+    Sched c;
+    c.split = q.split;
+    c.wpc = q.workgroups_per_cu;
+    c.fused = q.fused;
+    c.theta_tiles = q.theta_tiles;
+    c.phi_groups = q.phi_groups;
+    for (int i = 0; i < 9; ++i) {
+        const int w = q.theta_cols[i];
+        if (w == 0) continue;
+        if (w != 4 && w != 8 && w != 16 && w != 32 && w != 64) return SPHFILT_EINVAL;
+        c.cols[kLines[i]] = w;
+    }
+    DeviceGuard g(batch->device);
+    if (!g.ok) return SPHFILT_EDEVICE;
+    return set_sched(batch, c);
+}
+
+int sphfilt_batch_get_schedule_ex(sphfilt_batch batch, sphfilt_batch_schedule *sched)
+{
+    if (!batch || !sched) return SPHFILT_EINVAL;
+    sphfilt_batch_schedule q{};
+    q.split = batch->split;
+    q.workgroups_per_cu = effective_wpc(batch, batch->wpc);
+    q.fused = batch->fused;
+    q.theta_tiles = batch->theta_tiles;
+    q.phi_groups = batch->phi_groups;
+    for (int i = 0; i < 9; ++i) {
+        auto it = batch->theta_cols.find(kLines[i]);
+        q.theta_cols[i] = it == batch->theta_cols.end() ? 0 : it->second;
+    }
+    q.tuned_us = batch->tuned_us;
+    q.default_us = batch->default_us;
+    *sched = q;
     return SPHFILT_OK;
 }
 

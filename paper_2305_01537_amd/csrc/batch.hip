@@ -39,7 +39,8 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
 {
     if (n_work <= 0) return hipSuccess;
     const BatchArgs a{work, n_work, patches, ins, outs, th, ph, fc, shells, counters,
-                      need, ticket, error, eneg, use_deps, spin_limit, need_bias};
+                      need, ticket, error, eneg, use_deps, spin_limit, need_bias,
+                      use_deps && grid > 0 ? 1 : 0};
     switch (variant & 3) {
     case 0: return launch_batch_plain(grid, a, s);
     case kBatchHybrid: return launch_batch_hybrid(grid, a, s);

@@ -20,6 +20,9 @@ namespace sphfilt {
 //   shell_off, n_shells
 //             the distinct global shell ids this item writes (first pass) or
 //             touches (second pass), in the batch's shell list.
+//   count     theta: meridian tiles [tile, tile + count) of the same shells;
+//             phi: n_valid ring pairs in ceil(n_valid / L) workgroup rounds of
+//             L = 256 / lanes-per-line pairs (count is then unused: 1).
 struct BatchWork {
     int32_t patch;
     int16_t pass;
@@ -30,7 +33,7 @@ struct BatchWork {
     int32_t shell_off;
     int32_t n_shells;
     int32_t aux;
-    int32_t pad;
+    int32_t count;
 };
 
 // Per-patch constants of the batch kernel.
@@ -64,6 +67,7 @@ struct BatchArgs {
     int use_deps;
     int spin_limit;
     int need_bias;        // added to every wait target (0; 1 only to force a give-up in tests)
+    int defer;            // persistent one-kernel form: first-pass items signal in batches
 };
 
 // The four kernel instances (HYB, MIXED), each in its own translation unit:
@@ -91,6 +95,8 @@ hipError_t launch_batch(int grid, const BatchWork *work, int n_work, const Batch
                         const int *need,
                         int *ticket, int *error, const double *eneg, int use_deps, int spin_limit,
                         int need_bias, int variant, hipStream_t s);
+// (the persistent form, grid > 0, with use_deps defers its signals; see
+// flush_pending in batch_kernels.h)
 // Resident 256-lane workgroups of the persistent batch kernel instance
 // `variant` per compute unit.
 int batch_blocks_per_cu(int variant);

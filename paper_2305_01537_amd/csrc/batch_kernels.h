@@ -61,7 +61,7 @@ static_assert(batch_lds_fits<32, false>() && batch_lds_fits<64, false>() &&
 // for the plain MIXED form.  Persistent: two for the plain power-of-two
 // form, one for the others.
 template <bool HYB, bool MIXED>
-constexpr int oneshot_waves() { return HYB || MIXED ? 2 : 1; }
+constexpr int oneshot_waves() { return 2; }
 template <bool HYB, bool MIXED>
 constexpr int persistent_waves() { return HYB || MIXED ? 1 : 2; }
 
@@ -71,15 +71,30 @@ __device__ __forceinline__ HybridArgs batch_hybrid(const BatchPatchDev &pd)
     return HybridArgs{pd.det_eps, pd.det_threshold, nullptr, 0, pd.hybrid};
 }
 
+// A theta item runs `count` consecutive meridian tiles of its shells, a phi
+// item its ring pairs in rounds of one workgroup's worth (the schedule's
+// tiles and ring groups per item; the loops are workgroup-uniform, and each
+// worker starts with a barrier before it touches LDS).
+// The lane index goes through an opaque move at every round, so that the
+// per-lane index math of a round is recomputed rather than kept live across
+// rounds (which would raise the kernel's register count).
+__device__ __forceinline__ int opaque_lane(int lane)
+{
+    unsigned v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "v"((unsigned)lane));
+    return (int)v;
+}
+
 template <int N, bool HYB>
 __device__ __forceinline__ void theta_item(const BatchWork &w, const BatchPatchDev &pd,
                                            const double *src, double *dst,
                                            const ThetaItem *th, const double *eneg, double *lds,
                                            double *etab, int *flags, int lane)
 {
-    theta_block<N, lines_per_256<N>(), HYB>(src, dst, th + w.first, w.n_valid, pd.cp_log2, w.tile,
-                                       pd.n_theta, pd.n_phi, pd.tw_theta, eneg, lds, etab, flags,
-                                       batch_hybrid(pd), lane);
+    for (int k = 0; k < w.count; ++k)
+        theta_block<N, lines_per_256<N>(), HYB>(src, dst, th + w.first, w.n_valid, pd.cp_log2,
+                                               w.tile + k, pd.n_theta, pd.n_phi, pd.tw_theta, eneg,
+                                               lds, etab, flags, batch_hybrid(pd), opaque_lane(lane));
 }
 
 template <int N, bool HYB>
@@ -88,8 +103,10 @@ __device__ __forceinline__ void phi_item(const BatchWork &w, const BatchPatchDev
                                          const double *eneg, double *lds, double *etab, int *flags,
                                          int lane)
 {
-    phi_block<N, lines_per_256<N>(), HYB>(src, dst, ph + w.first, w.n_valid, pd.n_theta, pd.tw_phi,
-                                     eneg, lds, etab, flags, batch_hybrid(pd), lane);
+    constexpr int L = lines_per_256<N>();
+    for (int g = 0; g < w.n_valid; g += L)
+        phi_block<N, L, HYB>(src, dst, ph + w.first + g, min(L, w.n_valid - g), pd.n_theta,
+                             pd.tw_phi, eneg, lds, etab, flags, batch_hybrid(pd), opaque_lane(lane));
 }
 
 template <int N, bool HYB>
@@ -195,7 +212,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
         }
     }
 
-    if (a.use_deps && !w.second && w.n_shells > 0) {
+    if (a.use_deps && !w.second && w.n_shells > 0 && !a.defer) {
         // Every wave waits until its own stores have reached the L2; one lane
         // then makes the L2 contents visible device-wide with a single
         // device-scope release (it acts on the whole cache) and bumps the
@@ -209,6 +226,34 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, int k, int lane, do
                                        __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// Deferred signals of the persistent one-kernel schedule: a workgroup keeps
+// the first-pass items it finished in `pending` (LDS) and signals them all
+// with one device-scope release when the list is full, before it waits on a
+// second-pass item, and when it runs out of tickets.  A workgroup never waits
+// while holding unsignalled items, so every wait still ends.
+constexpr int kPendingItems = 32;
+
+__device__ __forceinline__ void flush_pending(const BatchArgs &a, int *pending, int *n_pending,
+                                              int lane)
+{
+    const int n = *n_pending;
+    if (n == 0) return;                         // workgroup-uniform (read after a barrier)
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (lane < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (int i = 0; i < n; ++i) {
+            const BatchWork &w = a.work[pending[i]];
+            for (int j = lane; j < w.n_shells; j += 64)
+                __hip_atomic_fetch_add(a.counters + a.shells[w.shell_off + j], 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    if (lane == 0) *n_pending = 0;
+    __syncthreads();
 }
 
 // Take the next ticket (workgroup-uniform).
@@ -255,13 +300,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_
     __shared__ double etab[129];
     __shared__ int flags[64];
     __shared__ int cur, gave_up;
+    __shared__ int pending[kPendingItems], n_pending;
+    if (threadIdx.x == 0) n_pending = 0;
     for (;;) {
         const int k = next_ticket(a.ticket, &cur);
         if (k >= a.n_work) break;
         unsigned lane;
         asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((unsigned)threadIdx.x));
+        if (a.defer) {
+            // signal what this workgroup finished before it may wait
+            const BatchWork &w = a.work[k];
+            if (w.second || n_pending == kPendingItems) flush_pending(a, pending, &n_pending, (int)lane);
+        }
         run_item<HYB, MIXED>(a, k, (int)lane, lds, etab, flags, &gave_up);
+        if (a.defer && !a.work[k].second && a.work[k].n_shells > 0) {
+            __syncthreads();
+            if (lane == 0) pending[n_pending++] = k;
+            __syncthreads();
+        }
     }
+    if (a.defer) flush_pending(a, pending, &n_pending, (int)threadIdx.x);
 }
 
 // Launch instance <HYB, MIXED>: grid > 0 persistent workgroups, else one

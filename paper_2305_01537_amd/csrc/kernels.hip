@@ -14,8 +14,9 @@ namespace sphfilt {
 // [0, shell_groups) run shell_block on `shells`, the rest run phi_block
 // (256/N2 ring pairs each) on `rings`.  The two sets touch different shells,
 // so one launch lets the ring-pair workgroups stream while the shell
-// workgroups load, filter and store their shells.
-template <int N, bool ADJ, bool HYB>
+// workgroups load, filter and store their shells.  MFMA: the shells' theta
+// pass as the circulant product (theta_gemm.h).
+template <int N, bool ADJ, bool HYB, bool MFMA>
 __global__ __launch_bounds__(256) void shell_phi_kernel(
     const double *in, double *out, const ThetaItem *__restrict__ shells,
     const double *__restrict__ ring_c, int n_shells, int shell_groups,
@@ -28,16 +29,63 @@ __global__ __launch_bounds__(256) void shell_phi_kernel(
     __shared__ double lds[S::lds];
     __shared__ double etab[N / 2 + 1];
     __shared__ int flags[LINES];
+    __shared__ double gaux[MFMA ? shell_gemm_aux<N>() : 1];
     if ((int)blockIdx.x < shell_groups) {
         const int first = blockIdx.x * S::shells;
-        shell_block<N, ADJ, HYB>(in, out, shells + first, ring_c + (size_t)first * S::lines,
-                                 min(S::shells, n_shells - first), tw, eneg, lds, etab, flags, ht,
-                                 hp, threadIdx.x);
+        shell_block<N, ADJ, HYB, MFMA>(in, out, shells + first, ring_c + (size_t)first * S::lines,
+                                       min(S::shells, n_shells - first), tw, eneg, lds, etab,
+                                       flags, ht, hp, threadIdx.x, gaux);
     } else {
         const int first = ((int)blockIdx.x - shell_groups) * LINES;
         phi_block<N, LINES, HYB>(in, out, rings + first, min(LINES, n_rings - first), N / 2, tw,
                                  eneg, lds, etab, flags, hp, threadIdx.x);
     }
+}
+
+// The theta pass alone as the circulant product, on grids with n_phi =
+// 2 n_theta = N in {32, 64}: each workgroup stages S = ShellShape<N>::shells
+// whole shells in LDS (contiguous loads), forms their circulants, multiplies
+// on the matrix cores and stores the results straight from the accumulators
+// (each store instruction covers 16 consecutive doubles of 4 rows).  Items
+// are active (non-identity) shells of plain kinds.
+template <int N>
+__global__ __launch_bounds__(256) void theta_gemm_kernel(const double *in, double *out,
+                                                         const ThetaItem *__restrict__ items,
+                                                         int n_items, const Twiddle *__restrict__ tw,
+                                                         const double *__restrict__ eneg)
+{
+    using S = ShellShape<N>;
+    constexpr int K = N / 2, SH = S::shells;
+    constexpr size_t shell_pts = (size_t)N * N / 2;
+    __shared__ double lds[S::lds];
+    __shared__ double etab[N / 2 + 1];
+    __shared__ double gaux[shell_gemm_aux<N>()];
+    const int lane = threadIdx.x;
+    const int first = blockIdx.x * SH;
+    const int n_valid = min(SH, n_items - first);
+    const ThetaItem *it = items + first;
+    stage_exp_table<N>(etab, eneg, lane);
+    const int us = lane / S::lanes;
+    const bool valid_s = us < n_valid;
+    const size_t base_s = valid_s ? (size_t)it[us].shell * shell_pts : 0;
+    cplx v[Split<N>::N1];
+    shell_stage<N, true>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
+    __syncthreads();
+    double *fq = gaux, *cosd = gaux + SH * (N / 2 + 1), *cvec = cosd + N;
+    shell_circulants<N, SH>(it, n_valid, tw, etab, fq, cosd, cvec, lane);
+    auto sign = [&](int sh) { return (it[sh].flags & kFlagOddParity) ? -1.0 : 1.0; };
+    dv4 acc[gemm_tiles_per_wave<N, SH>()];
+    shell_gemm<N, SH>(cvec, n_valid, lane, acc, [&](int sh, int m, int k, bool first_half) {
+        const double *sb = lds + sh * S::stride;
+        return first_half ? sb[m * S::row + k] : sign(sh) * sb[(N - 1 - m) * S::row + K + k];
+    });
+    shell_gemm_results<N, SH>(acc, n_valid, lane, [&](int sh, int n, int k, double y) {
+        double *dst = out + (size_t)it[sh].shell * shell_pts;
+        if (n < N / 2)
+            st_stream<SPHFILT_NT_STORE_THETA != 0>(dst + (size_t)n * N + k, y);
+        else
+            st_stream<SPHFILT_NT_STORE_THETA != 0>(dst + (size_t)(N - 1 - n) * N + K + k, sign(sh) * y);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -120,7 +168,7 @@ int shells_per_group(int n_phi)
 }
 
 
-template <int N>
+template <int N, bool MFMA>
 static hipError_t shell_phi_go(bool adjoint, const double *in, double *out,
                                const ThetaItem *shells, const double *ring_c, int n_shells,
                                const PhiItem *rings, int n_rings, const Twiddle *tw,
@@ -132,8 +180,8 @@ static hipError_t shell_phi_go(bool adjoint, const double *in, double *out,
     const dim3 grid((unsigned)(groups + (n_rings + LINES - 1) / LINES)), block(256);
     const bool hyb = ht.present != 0;
 #define SPHFILT_SHELL_PHI(A, H)                                                                    \
-    shell_phi_kernel<N, A, H><<<grid, block, 0, s>>>(in, out, shells, ring_c, n_shells, groups,    \
-                                                     rings, n_rings, tw, eneg, ht, hp)
+    shell_phi_kernel<N, A, H, MFMA && !H><<<grid, block, 0, s>>>(in, out, shells, ring_c, n_shells, \
+                                                                 groups, rings, n_rings, tw, eneg, ht, hp)
     if (adjoint) {
         if (hyb) SPHFILT_SHELL_PHI(true, true); else SPHFILT_SHELL_PHI(true, false);
     } else {
@@ -143,20 +191,46 @@ static hipError_t shell_phi_go(bool adjoint, const double *in, double *out,
     return hipGetLastError();
 }
 
+bool theta_gemm_ok(int n_theta, int n_phi)
+{
+    return n_phi == 2 * n_theta && (n_phi == 32 || n_phi == 64);
+}
+
 hipError_t launch_shell_phi(bool adjoint, int n_theta, int n_phi, const double *in, double *out,
                             const ThetaItem *shells, const double *ring_c, int n_shells,
                             const PhiItem *rings, int n_rings, const Twiddle *tw,
                             const double *eneg, const HybridArgs &ht, const HybridArgs &hp,
-                            hipStream_t s)
+                            hipStream_t s, bool mfma)
 {
     if (n_shells < 0 || n_rings < 0 || !shell_fusable(n_theta, n_phi)) return hipErrorInvalidValue;
+    if (mfma && (!theta_gemm_ok(n_theta, n_phi) || ht.present)) return hipErrorInvalidValue;
     if (n_shells + n_rings == 0) return hipSuccess;
     switch (n_phi) {
-    case 32: return shell_phi_go<32>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
-    case 64: return shell_phi_go<64>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
-    case 128: return shell_phi_go<128>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
+    case 32:
+        return mfma ? shell_phi_go<32, true>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s)
+                    : shell_phi_go<32, false>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
+    case 64:
+        return mfma ? shell_phi_go<64, true>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s)
+                    : shell_phi_go<64, false>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
+    case 128: return shell_phi_go<128, false>(adjoint, in, out, shells, ring_c, n_shells, rings, n_rings, tw, eneg, ht, hp, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_theta_gemm(int n_theta, int n_phi, const double *in, double *out,
+                             const ThetaItem *items, int n_items, const Twiddle *tw,
+                             const double *eneg, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    if (!theta_gemm_ok(n_theta, n_phi)) return hipErrorInvalidValue;
+    if (n_phi == 32) {
+        const unsigned g = (unsigned)((n_items + ShellShape<32>::shells - 1) / ShellShape<32>::shells);
+        theta_gemm_kernel<32><<<g, 256, 0, s>>>(in, out, items, n_items, tw, eneg);
+    } else {
+        const unsigned g = (unsigned)((n_items + ShellShape<64>::shells - 1) / ShellShape<64>::shells);
+        theta_gemm_kernel<64><<<g, 256, 0, s>>>(in, out, items, n_items, tw, eneg);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace sphfilt

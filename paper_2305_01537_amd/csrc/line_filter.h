@@ -10,6 +10,7 @@
 #pragma once
 #include "fft_core.h"
 #include "sphfilt_internal.h"
+#include "theta_gemm.h"
 
 #include <cmath>
 
@@ -740,15 +741,25 @@ __device__ __forceinline__ void shell_phi_io(cplx (&v)[Split<N>::N1], double *sb
 
 // items: the workgroup's shells (n_valid of them); ring_c: their phi cutoffs,
 // lines per shell.  ht / hp: hybrid arguments of the theta and phi passes.
-template <int N, bool ADJ, bool HYB>
+// MFMA (plain kinds, N = 32 or 64 only): the theta pass is the circulant
+// product of theta_gemm.h on the staged shells instead of the line FFTs;
+// gaux then holds its tables (shell_gemm_aux<N>() doubles).
+template <int N>
+constexpr int shell_gemm_aux()
+{
+    return ShellShape<N>::shells * (N / 2 + 1) + N + ShellShape<N>::shells * N;
+}
+
+template <int N, bool ADJ, bool HYB, bool MFMA = false>
 __device__ __forceinline__ void shell_block(const double *in, double *out,
                                             const ThetaItem *__restrict__ items,
                                             const double *__restrict__ ring_c, int n_valid,
                                             const Twiddle *__restrict__ tw,
                                             const double *__restrict__ eneg, double *lds,
                                             double *etab, int *flags, const HybridArgs &ht,
-                                            const HybridArgs &hp, int lane)
+                                            const HybridArgs &hp, int lane, double *gaux = nullptr)
 {
+    static_assert(!MFMA || (!HYB && (N == 32 || N == 64)), "circulant theta: plain kinds, N = 32, 64");
     using S = ShellShape<N>;
     constexpr int N1 = S::N1, N2 = S::N2, C = 256 / N2;
     constexpr size_t shell_pts = (size_t)N * N / 2;
@@ -799,11 +810,37 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         filter_line<N1, N2, HYB>(v, tp, ka, kb, mixed, c_p, L, tw, etab);
     };
 
+    // the theta pass on the staged shells, ending with their contents updated
+    // (no trailing barrier)
+    auto theta_pass = [&]() {
+        if constexpr (MFMA) {
+            constexpr int K = N / 2, SH = S::shells;
+            double *fq = gaux, *cosd = gaux + SH * (N / 2 + 1), *cvec = cosd + N;
+            shell_circulants<N, SH>(items, n_valid, tw, etab, fq, cosd, cvec, lane);
+            dv4 acc[gemm_tiles_per_wave<N, SH>()];
+            auto sign = [&](int sh) { return (items[sh].flags & kFlagOddParity) ? -1.0 : 1.0; };
+            shell_gemm<N, SH>(cvec, n_valid, lane, acc, [&](int sh, int m, int k, bool first) {
+                const double *sb = lds + sh * S::stride;
+                return first ? sb[m * S::row + k] : sign(sh) * sb[(N - 1 - m) * S::row + K + k];
+            });
+            __syncthreads();
+            shell_gemm_results<N, SH>(acc, n_valid, lane, [&](int sh, int n, int k, double y) {
+                double *sb = lds + sh * S::stride;
+                if (n < N / 2)
+                    sb[n * S::row + k] = y;
+                else
+                    sb[(N - 1 - n) * S::row + K + k] = sign(sh) * y;
+            });
+        } else {
+            shell_theta_io<N, false>(v, sb_t, tt, kr, sgn);
+            __syncthreads();
+            theta_filter();
+            shell_theta_io<N, true>(v, sb_t, tt, kr, sgn);
+        }
+    };
+
     if constexpr (!ADJ) {
-        shell_theta_io<N, false>(v, sb_t, tt, kr, sgn);
-        __syncthreads();
-        theta_filter();
-        shell_theta_io<N, true>(v, sb_t, tt, kr, sgn);
+        theta_pass();
         __syncthreads();
         shell_phi_io<N, false>(v, sb_p, tp, j);
         __syncthreads();
@@ -815,10 +852,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         phi_filter();
         shell_phi_io<N, true>(v, sb_p, tp, j);
         __syncthreads();
-        shell_theta_io<N, false>(v, sb_t, tt, kr, sgn);
-        __syncthreads();
-        theta_filter();
-        shell_theta_io<N, true>(v, sb_t, tt, kr, sgn);
+        theta_pass();
     }
     __syncthreads();
     shell_stage<N, false>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);

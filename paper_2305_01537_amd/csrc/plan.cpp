@@ -16,15 +16,18 @@
 #include "../../include/sphfilt.h"
 #include "host_tables.h"
 #include "sphfilt_internal.h"
+#include "tune_cache.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 using namespace sphfilt;
@@ -64,9 +67,12 @@ struct sphfilt_plan_s {
     DeviceTables dev;
     int theta_cols, phi_lines;
     int fused;              // fuse shells where the grid allows it
+    int theta_mfma;         // theta pass as the circulant product on the matrix cores
     int overlap;            // 0 off, 1 auto, 2 always: independent rings on the side stream
     HybridArgs hybrid;      // detector parameters; dec / replay set per call
     SideStream side;
+    uint64_t params_hash;   // grid, fields and cutoffs (the tune cache key, with the GPU arch)
+    double tuned_us, default_us;
 };
 
 namespace {
@@ -107,6 +113,8 @@ HybridArgs pass_args(const sphfilt_plan p, unsigned char *dec, const Decisions &
 // The theta pass (or the phi pass) over items [0, n) of a list whose first
 // n_hyb items are hybrid: those with the hybrid-capable kernel, the rest with
 // the plain one.
+// With the circulant variant the plain active items [n_hyb, n_active) go to
+// the matrix-core kernel (the item lists put the active items first).
 hipError_t theta_split(sphfilt_plan p, const double *in, double *out, const ThetaItem *items, int n,
                        int n_hyb, const Decisions &d, hipStream_t s)
 {
@@ -115,8 +123,16 @@ hipError_t theta_split(sphfilt_plan p, const double *in, double *out, const Thet
     if (nh > 0)
         e = launch_theta(2 * p->n_theta, p->theta_cols, in, out, items, nh, p->n_theta, p->n_phi,
                          p->dev.tw_theta, p->dev.eneg, pass_args(p, d.theta, d, true), s);
-    if (e == hipSuccess && n > nh)
-        e = launch_theta(2 * p->n_theta, p->theta_cols, in, out, items + nh, n - nh, p->n_theta,
+    int done = nh;
+    if (p->theta_mfma && e == hipSuccess) {
+        const int na = n < p->host.theta_active ? n : p->host.theta_active;
+        if (na > nh)
+            e = launch_theta_gemm(p->n_theta, p->n_phi, in, out, items + nh, na - nh,
+                                  p->dev.tw_theta, p->dev.eneg, s);
+        done = na > nh ? na : nh;
+    }
+    if (e == hipSuccess && n > done)
+        e = launch_theta(2 * p->n_theta, p->theta_cols, in, out, items + done, n - done, p->n_theta,
                          p->n_phi, p->dev.tw_theta, p->dev.eneg, pass_args(p, d.theta, d, false), s);
     return e;
 }
@@ -184,7 +200,7 @@ int apply_fused(sphfilt_plan p, bool adjoint, const double *in, double *out, con
         e = launch_shell_phi(adjoint, p->n_theta, p->n_phi, in, out, p->dev.theta + nh,
                              p->dev.fused_c + (size_t)nh * lines, t.n_fused - nh, p->dev.phi_rest,
                              n_rings, p->dev.tw_phi, p->dev.eneg, pass_args(p, d.theta, d, false),
-                             pass_args(p, d.phi, d, false), s);
+                             pass_args(p, d.phi, d, false), s, p->theta_mfma != 0);
     return e == hipSuccess ? SPHFILT_OK : SPHFILT_EDEVICE;
 }
 
@@ -290,6 +306,167 @@ int apply_one(sphfilt_plan p, Pass which, const double *in, double *out, void *s
     return run_pass(p, which, in, out, in != out, Decisions{}, (hipStream_t)stream);
 }
 
+uint64_t hash_params(int n_r, int n_theta, int n_phi, int n_fields, const int *parity,
+                     const sphfilt_cutoff *cut)
+{
+    uint64_t h = kFnvSeed;
+    const char tag[] = "plan";
+    h = fnv1a(h, tag, sizeof(tag));
+    const int dims[4] = {n_r, n_theta, n_phi, n_fields};
+    h = fnv1a(h, dims, sizeof(dims));
+    h = fnv1a(h, parity, sizeof(int) * n_fields);
+    h = fnv1a(h, cut->L, sizeof(double) * n_fields);
+    const int has[2] = {cut->rho != nullptr, cut->kind != nullptr};
+    h = fnv1a(h, has, sizeof(has));
+    if (cut->rho) h = fnv1a(h, cut->rho, sizeof(double) * n_r);
+    if (cut->kind) h = fnv1a(h, cut->kind, sizeof(int) * n_fields);
+    const double d[3] = {cut->floor_modes, cut->detector_eps, cut->detector_threshold};
+    return fnv1a(h, d, sizeof(d));
+}
+
+// ---- the plan's autotuner --------------------------------------------------
+struct PlanSched {
+    int theta_cols, phi_lines, fused, theta_mfma, overlap;
+    bool operator==(const PlanSched &o) const
+    {
+        return theta_cols == o.theta_cols && phi_lines == o.phi_lines && fused == o.fused &&
+               theta_mfma == o.theta_mfma && overlap == o.overlap;
+    }
+};
+
+PlanSched plan_sched(const sphfilt_plan p)
+{
+    return PlanSched{p->theta_cols, p->phi_lines, p->fused, p->theta_mfma, p->overlap};
+}
+
+void set_plan_sched(sphfilt_plan p, const PlanSched &c)
+{
+    p->theta_cols = c.theta_cols;
+    p->phi_lines = c.phi_lines;
+    p->fused = c.fused;
+    p->theta_mfma = c.theta_mfma;
+    p->overlap = c.overlap;
+}
+
+// Median of `reps` forward filters in place on x (HIP events on s).
+int time_plan(sphfilt_plan p, double *x, hipStream_t s, int reps, double *us)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SPHFILT_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SPHFILT_EDEVICE; }
+    std::vector<float> t;
+    int rc = SPHFILT_OK;
+    for (int r = 0; r < reps + 2 && !rc; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = SPHFILT_EDEVICE; break; }
+        rc = apply_two(p, Pass::Theta, Pass::Phi, x, x, Decisions{}, s);
+        if (rc) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = SPHFILT_EDEVICE;
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (r >= 2) t.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    *us = 1000.0 * t[t.size() / 2];
+    return SPHFILT_OK;
+}
+
+// Coordinate descent from the plan's current schedule over the theta tile
+// width, the ring pairs per phi workgroup, fused shells (where the grid has
+// them), the theta variant (where the circulant product applies) and the
+// overlap mode (where the plan has a side stream); each candidate is timed
+// as a forward filter in place on zeroed scratch fields of the plan's size.
+int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
+{
+    const size_t n = (size_t)p->n_fields * p->n_r * p->n_theta * p->n_phi;
+    double *x = nullptr;
+    hipError_t e = hipMalloc((void **)&x, sizeof(double) * n);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? SPHFILT_ENOMEM : SPHFILT_EDEVICE;
+    hipStream_t s = nullptr;
+    int rc = SPHFILT_OK;
+    if (hipMemset(x, 0, sizeof(double) * n) != hipSuccess ||
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        rc = SPHFILT_EDEVICE;
+    const PlanSched start = plan_sched(p);
+    PlanSched best = start;
+    double best_us = 1e300, default_us = -1.0;
+    std::vector<PlanSched> tried;
+    auto try_sched = [&](const PlanSched &c) {
+        if (rc || std::find(tried.begin(), tried.end(), c) != tried.end()) return;
+        tried.push_back(c);
+        set_plan_sched(p, c);
+        double us = 0;
+        rc = time_plan(p, x, s, 5, &us);
+        if (rc) return;
+        if (default_us < 0) default_us = us;
+        if (us < best_us) {
+            best_us = us;
+            best = c;
+        }
+    };
+    try_sched(start);
+    const int nl = 2 * p->n_theta;
+    for (int w : {4, 8, 16, 32, 64})
+        if (theta_shape_ok(nl, w, p->n_phi)) {
+            PlanSched c = best;
+            c.theta_cols = w;
+            try_sched(c);
+        }
+    for (int l : {4, 8, 16, 32, 64})
+        if (phi_shape_ok(p->n_phi, l)) {
+            PlanSched c = best;
+            c.phi_lines = l;
+            try_sched(c);
+        }
+    if (p->host.n_fused > 0)
+        for (int f : {0, 1}) {
+            PlanSched c = best;
+            c.fused = f;
+            try_sched(c);
+        }
+    if (theta_gemm_ok(p->n_theta, p->n_phi))
+        for (int m : {0, 1}) {
+            PlanSched c = best;
+            c.theta_mfma = m;
+            try_sched(c);
+        }
+    if (p->side.state == 1)
+        for (int o : {0, 1, 2}) {
+            PlanSched c = best;
+            c.overlap = o;
+            try_sched(c);
+        }
+    if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    (void)hipFree(x);
+    set_plan_sched(p, rc ? start : best);
+    if (rc) return rc;
+    p->tuned_us = best_us;
+    p->default_us = default_us;
+    if (cache_path) {
+        TuneFields f;
+        f["what"] = tune_str("plan");
+        f["arch"] = tune_str(arch);
+        f["theta_cols"] = tune_num(best.theta_cols);
+        f["phi_lines"] = tune_num(best.phi_lines);
+        f["fused"] = tune_num(best.fused);
+        f["theta_variant"] = tune_num(best.theta_mfma);
+        f["overlap"] = tune_num(best.overlap);
+        f["us"] = tune_num(best_us);
+        f["default_us"] = tune_num(default_us);
+        const uint64_t sig = fnv1a(p->params_hash, arch.data(), arch.size());
+        if (!tune_cache_put(cache_path, hex64(sig), f)) return SPHFILT_EINVAL;
+    }
+    return SPHFILT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -328,7 +505,10 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
     p->hybrid = hybrid_args(cut, n_fields);
     p->phi_lines = default_phi_lines(n_phi);
     p->fused = 1;
+    p->theta_mfma = 0;
     p->overlap = 1;
+    p->params_hash = hash_params(n_r, n_theta, n_phi, n_fields, parity, cut);
+    p->tuned_us = p->default_us = -1.0;
     try {
         build_items(n_r, n_theta, n_phi, n_fields, parity, cut, &p->host);
         if (hipGetDevice(&p->device) != hipSuccess) rc = SPHFILT_EDEVICE;
@@ -443,6 +623,63 @@ int sphfilt_plan_get_overlap(sphfilt_plan plan, int *mode)
 {
     if (!plan || !mode) return SPHFILT_EINVAL;
     *mode = plan->overlap;
+    return SPHFILT_OK;
+}
+
+int sphfilt_plan_tune(sphfilt_plan plan, const char *tune_cache_path)
+{
+    if (!plan) return SPHFILT_EINVAL;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return SPHFILT_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, plan->device) != hipSuccess) return SPHFILT_EDEVICE;
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    const char *cache = tune_cache_path ? tune_cache_path : tune_cache_default();
+    if (cache) {
+        TuneFields f;
+        const uint64_t sig = fnv1a(plan->params_hash, arch.data(), arch.size());
+        std::string what;
+        PlanSched c{};
+        if (tune_cache_get(cache, hex64(sig), &f) && tune_string(f, "what", &what) && what == "plan" &&
+            tune_int(f, "theta_cols", &c.theta_cols) && tune_int(f, "phi_lines", &c.phi_lines) &&
+            tune_int(f, "fused", &c.fused) && tune_int(f, "theta_variant", &c.theta_mfma) &&
+            tune_int(f, "overlap", &c.overlap) &&
+            theta_shape_ok(2 * plan->n_theta, c.theta_cols, plan->n_phi) &&
+            phi_shape_ok(plan->n_phi, c.phi_lines) && (c.fused == 0 || c.fused == 1) &&
+            (c.theta_mfma == 0 || (c.theta_mfma == 1 && theta_gemm_ok(plan->n_theta, plan->n_phi))) &&
+            c.overlap >= 0 && c.overlap <= 2) {
+            set_plan_sched(plan, c);
+            if (!tune_double(f, "us", &plan->tuned_us)) plan->tuned_us = -1.0;
+            if (!tune_double(f, "default_us", &plan->default_us)) plan->default_us = -1.0;
+            return SPHFILT_OK;
+        }
+    }
+    return tune_plan(plan, arch, cache);
+}
+
+int sphfilt_plan_tuned_times(sphfilt_plan plan, double *tuned_us, double *default_us)
+{
+    if (!plan) return SPHFILT_EINVAL;
+    if (tuned_us) *tuned_us = plan->tuned_us;
+    if (default_us) *default_us = plan->default_us;
+    return SPHFILT_OK;
+}
+
+int sphfilt_plan_set_theta_variant(sphfilt_plan plan, int variant)
+{
+    if (!plan || (variant != SPHFILT_THETA_FFT && variant != SPHFILT_THETA_MFMA)) return SPHFILT_EINVAL;
+    if (variant == SPHFILT_THETA_MFMA && !theta_gemm_ok(plan->n_theta, plan->n_phi))
+        return SPHFILT_EUNSUPPORTED;
+    plan->theta_mfma = variant == SPHFILT_THETA_MFMA;
+    return SPHFILT_OK;
+}
+
+int sphfilt_plan_get_theta_variant(sphfilt_plan plan, int *variant)
+{
+    if (!plan || !variant) return SPHFILT_EINVAL;
+    *variant = plan->theta_mfma ? SPHFILT_THETA_MFMA : SPHFILT_THETA_FFT;
     return SPHFILT_OK;
 }
 

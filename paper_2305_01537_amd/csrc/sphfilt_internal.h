@@ -68,11 +68,20 @@ hipError_t launch_phi(int n_line, int lines, const double *in, double *out, cons
 // ring_c: the n_theta/2 phi cutoffs (j ascending) of each shell.  ht / hp:
 // hybrid arguments of the theta and phi passes.  The twiddle table is the one
 // of length n_phi (= 2 n_theta).
+// mfma: the fused shells' theta pass as the circulant product (plain kinds,
+// needs theta_gemm_ok; a launch with hybrid shells must pass false).
 hipError_t launch_shell_phi(bool adjoint, int n_theta, int n_phi, const double *in, double *out,
                             const ThetaItem *shells, const double *ring_c, int n_shells,
                             const PhiItem *rings, int n_rings, const Twiddle *tw,
                             const double *eneg, const HybridArgs &ht, const HybridArgs &hp,
-                            hipStream_t stream);
+                            hipStream_t stream, bool mfma = false);
+// The theta pass as the circulant product on the matrix cores, over active
+// shells of plain kinds, on grids with theta_gemm_ok (n_phi = 2 n_theta in
+// {32, 64}); tw: the twiddle table of length n_phi.
+bool theta_gemm_ok(int n_theta, int n_phi);
+hipError_t launch_theta_gemm(int n_theta, int n_phi, const double *in, double *out,
+                             const ThetaItem *items, int n_items, const Twiddle *tw,
+                             const double *eneg, hipStream_t stream);
 // n_phi = 2 n_theta in {32, 64, 128}: whole shells per 256-lane workgroup.
 bool shell_fusable(int n_theta, int n_phi);
 int shells_per_group(int n_phi);

@@ -18,7 +18,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import EXP, GAUSS, HYBRID, SHARP, SphfiltError, status_string  # noqa: F401
+from ._lib import (EXP, GAUSS, HYBRID, SHARP, THETA_FFT, THETA_MFMA, SphfiltError,  # noqa: F401
+                   status_string)
 
 
 def _as_int_array(v, n, name):
@@ -215,6 +216,29 @@ class Plan:
         run two passes; see sphfilt_plan_set_fused."""
         _lib.check("sphfilt_plan_set_fused", self._lib.sphfilt_plan_set_fused(self._h, int(bool(enable))))
 
+    def tune(self, cache_path: Optional[str] = None):
+        """Autotune the plan's launch settings (see sphfilt_plan_tune);
+        returns {"tuned_us", "default_us"}."""
+        path = None if cache_path is None else str(cache_path).encode()
+        _lib.check("sphfilt_plan_tune", self._lib.sphfilt_plan_tune(self._h, path))
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _lib.check("sphfilt_plan_tuned_times",
+                   self._lib.sphfilt_plan_tuned_times(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return {"tuned_us": a.value, "default_us": b.value}
+
+    def set_theta_variant(self, variant: int):
+        """THETA_FFT (default) or THETA_MFMA: the theta pass as the circulant
+        product on the matrix cores (grids with n_phi = 2 n_theta in {32, 64});
+        see sphfilt_plan_set_theta_variant."""
+        _lib.check("sphfilt_plan_set_theta_variant",
+                   self._lib.sphfilt_plan_set_theta_variant(self._h, int(variant)))
+
+    def get_theta_variant(self) -> int:
+        a = ctypes.c_int()
+        _lib.check("sphfilt_plan_get_theta_variant",
+                   self._lib.sphfilt_plan_get_theta_variant(self._h, ctypes.byref(a)))
+        return a.value
+
     def set_overlap(self, mode: int):
         """In place, run the rings that do not depend on the theta pass on a
         second stream of the plan: 0 never, 1 when they move >= 128 MiB (the
@@ -342,11 +366,29 @@ class Batch:
                    self._lib.sphfilt_batch_set_schedule(self._h, int(split), int(workgroups_per_cu)))
 
     def get_schedule(self):
-        a, b, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-        _lib.check("sphfilt_batch_get_schedule",
-                   self._lib.sphfilt_batch_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b),
-                                                        ctypes.byref(us)))
-        return {"split": a.value, "workgroups_per_cu": b.value, "tuned_us": us.value}
+        """The whole schedule (see sphfilt_batch_schedule): split,
+        workgroups_per_cu, fused, theta_tiles, phi_groups, theta_cols
+        ({line length: width} for the tuned widths), tuned_us, default_us."""
+        q = _lib.BatchSchedule()
+        _lib.check("sphfilt_batch_get_schedule_ex",
+                   self._lib.sphfilt_batch_get_schedule_ex(self._h, ctypes.byref(q)))
+        return {"split": q.split, "workgroups_per_cu": q.workgroups_per_cu, "fused": q.fused,
+                "theta_tiles": q.theta_tiles, "phi_groups": q.phi_groups,
+                "theta_cols": {n: q.theta_cols[i] for i, n in enumerate(_lib.THETA_LINES)
+                               if q.theta_cols[i]},
+                "tuned_us": q.tuned_us, "default_us": q.default_us}
+
+    def set_schedule_ex(self, split: int = 0, workgroups_per_cu: int = -1, fused: bool = True,
+                        theta_tiles: int = 1, phi_groups: int = 1, theta_cols=None):
+        """Set every schedule knob at once; theta_cols: {theta line length:
+        sub-tile width} (others keep their default width)."""
+        q = _lib.BatchSchedule()
+        q.split, q.workgroups_per_cu, q.fused = int(split), int(workgroups_per_cu), int(bool(fused))
+        q.theta_tiles, q.phi_groups = int(theta_tiles), int(phi_groups)
+        for n, w in (theta_cols or {}).items():
+            q.theta_cols[_lib.THETA_LINES.index(int(n))] = int(w)
+        _lib.check("sphfilt_batch_set_schedule_ex",
+                   self._lib.sphfilt_batch_set_schedule_ex(self._h, ctypes.byref(q)))
 
     def status(self) -> int:
         e = ctypes.c_int()
