@@ -5,8 +5,9 @@ One step = one forward double FFT filter (theta-pass then phi-pass) over the
 production share: 24 FP64 fields on a 256 x 128 x 256 (r, theta, phi) grid,
 with the paper's cutoff (cal-L = 3 on a uniform cell-centred radial grid),
 applied in place -- the way an evolution code filters its state once per
-Runge-Kutta substep, with the plan's default schedule (rings that do not
-depend on the theta pass overlapped on a second stream).  Inputs are seeded
+Runge-Kutta substep, with the launch settings the plan's autotuner picks
+(tile widths, ring pairs per workgroup, overlap of the rings that do not
+depend on the theta pass on a second stream).  Inputs are seeded
 synthetic fields already resident in HBM; four copies are rotated so no step
 finds its data in the 256 MB Infinity Cache from the step before.
 
@@ -507,6 +508,14 @@ def main():
     F, R, T, P = w.shape
     plan = Plan(R, T, P, F, parity=w.parity, L=w.L, rho=w.rho)
     st = plan.stats()
+    # the plan's autotuner picks its launch settings (before the workload is
+    # uploaded: it times candidates on scratch fields of the plan's size)
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        tune = plan.tune(os.path.join(d, "tune.json"))
+    plan_schedule = {"theta_cols": plan.get_schedule()[0], "phi_lines": plan.get_schedule()[1],
+                     "overlap": plan.get_overlap(), **tune}
+    log(f"plan tuner: {plan_schedule}")
     x0 = torch.from_numpy(w.x).to(dev)
     bufs = [x0] + [x0.clone() for _ in range(3)]
     torch.cuda.synchronize()
@@ -536,6 +545,7 @@ def main():
         f"phi {ms_phi:.4f} ms ({ph_bytes / ms_phi / 1e6:.1f} GB/s)")
 
     extra = {
+        "plan_schedule": plan_schedule,
         "theta_pass_ms": ms_theta, "phi_pass_ms": ms_phi,
         "algorithmic_bytes_per_step": st["bytes_forward_inplace"],
         "step_GBps": st["bytes_forward_inplace"] / (ms_fwd * 1e-3) / 1e9,

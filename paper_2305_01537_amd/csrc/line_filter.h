@@ -187,7 +187,9 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[NV], int t, int kind, doubl
 // line's LDS region P (2N doubles: real parts, then imaginary parts, natural
 // order), so one barrier serves both parts and each mode's factors are used
 // as soon as they are formed.  Lines with ka == kb get plain f Z.  All lanes
-// of the workgroup call this together.
+// of the workgroup call this together.  (Restricting the exchange to the
+// lines that mix two kinds saves nothing in the theta pass: one theta wave
+// holds lanes of every line of the workgroup, so its waves run both paths.)
 template <int N1, int N2, int NV>
 __device__ __forceinline__ void apply_mask_pair(cplx (&v)[NV], int t, int ka, int kb, double c,
                                                 const double *etab, double *P)
@@ -723,6 +725,44 @@ __device__ __forceinline__ void shell_theta_io(cplx (&v)[Split<N>::N1], double *
     });
 }
 
+// The theta layout straight from / to HBM (the shell at `base`, rows of N
+// doubles): the same positions as shell_theta_io, with no staging copy.  A
+// load or store instruction covers the lines' consecutive meridians of one
+// or two rows.  Invalid shells load zeros and store nothing.
+template <int N, bool LOAD>
+__device__ __forceinline__ void shell_theta_hbm(const double *in, double *out, size_t base,
+                                                cplx (&v)[Split<N>::N1], int t, int kr, double s,
+                                                bool valid)
+{
+    using S = ShellShape<N>;
+    constexpr int N1 = S::N1, N2 = S::N2, half = N / 2;
+    constexpr bool cached = theta_loads_cached<N>();
+    const int ki = kr + S::lines;
+    static_for<0, N1>([&](auto nn) {
+        constexpr int n1 = decltype(nn)::value;
+        constexpr bool first = n1 < N1 / 2;
+        const size_t row = first ? base + (size_t)(N2 * n1 + t) * N
+                                 : base + (size_t)(N - 1 - N2 * n1 - t) * N + half;
+        if constexpr (LOAD) {
+            if (!valid) {
+                v[n1] = cplx{0.0, 0.0};
+            } else if constexpr (first) {
+                v[n1] = cplx{ld_piece<cached>(in + row + kr), ld_piece<cached>(in + row + ki)};
+            } else {
+                v[n1] = cplx{s * ld_piece<cached>(in + row + kr), s * ld_piece<cached>(in + row + ki)};
+            }
+        } else if (valid) {
+            if constexpr (first) {
+                st_stream<true>(out + row + kr, v[n1].re);
+                st_stream<true>(out + row + ki, v[n1].im);
+            } else {
+                st_stream<true>(out + row + kr, s * v[n1].re);
+                st_stream<true>(out + row + ki, s * v[n1].im);
+            }
+        }
+    });
+}
+
 // phi layout: lane (p, t), t = lane % N2 fastest; line p packs rings j and
 // n_theta-1-j, j = p % lines, of staged shell p / lines.
 template <int N, bool WRITE>
@@ -765,20 +805,29 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
     constexpr size_t shell_pts = (size_t)N * N / 2;
     stage_exp_table<N>(etab, eneg, lane);
 
-    // staging
+    // Staging through LDS with contiguous HBM accesses is done on the phi
+    // side of the shell (the input of the adjoint order, the output of the
+    // forward order); the theta side loads or stores its lines straight in
+    // the theta layout (row segments, as the theta kernel does), saving one
+    // LDS round trip.  The circulant (MFMA) variant stages both sides.
+    constexpr bool theta_direct = !MFMA;
     const int us = lane / S::lanes;
     const bool valid_s = us < n_valid;
     const size_t base_s = valid_s ? (size_t)items[us].shell * shell_pts : 0;
     cplx v[N1];
-    shell_stage<N, true>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
-    __syncthreads();
 
     // theta layout
     const int pt = lane % C, tt = lane / C, ut = pt / S::lines, kr = pt % S::lines;
     const bool valid_t = ut < n_valid;
     const ThetaItem it = valid_t ? items[ut] : ThetaItem{0, 0, 0.0};
     const double sgn = (it.flags & kFlagOddParity) ? -1.0 : 1.0;
+    const size_t base_t = valid_t ? (size_t)it.shell * shell_pts : 0;
     double *sb_t = lds + ut * S::stride;
+
+    if (!(theta_direct && !ADJ)) {
+        shell_stage<N, true>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
+        __syncthreads();
+    }
     // phi layout
     const int tp = lane % N2, pp = lane / N2, up = pp / S::lines, j = pp % S::lines;
     const bool valid_p = up < n_valid;
@@ -831,11 +880,17 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
                 else
                     sb[(N - 1 - n) * S::row + K + k] = sign(sh) * y;
             });
+        } else if constexpr (!ADJ) {
+            // forward: the lines come from HBM, the result goes to the staging area
+            shell_theta_hbm<N, true>(in, out, base_t, v, tt, kr, sgn, valid_t);
+            theta_filter();
+            shell_theta_io<N, true>(v, sb_t, tt, kr, sgn);
         } else {
+            // adjoint: the lines come from the staging area, the result goes to HBM
             shell_theta_io<N, false>(v, sb_t, tt, kr, sgn);
             __syncthreads();
             theta_filter();
-            shell_theta_io<N, true>(v, sb_t, tt, kr, sgn);
+            shell_theta_hbm<N, false>(in, out, base_t, v, tt, kr, sgn, valid_t);
         }
     };
 
@@ -854,8 +909,10 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         __syncthreads();
         theta_pass();
     }
-    __syncthreads();
-    shell_stage<N, false>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
+    if (!(theta_direct && ADJ)) {
+        __syncthreads();
+        shell_stage<N, false>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
+    }
 }
 
 }  // namespace sphfilt
