@@ -530,8 +530,14 @@ def main():
     value = points / (ms_fwd * 1e-3)
 
     # ---- per-kernel launches (same data, same stream) for the roofline -----
-    ms_theta = time_loop(torch, lambda b: plan.apply_theta(b, out=b), bufs, args.steps, 2, stream)
-    ms_phi = time_loop(torch, lambda b: plan.apply_phi(b, out=b), bufs, args.steps, 2, stream)
+    # each pass alone with the default launch shape (16 meridian pairs per
+    # theta sub-tile, 16 ring pairs per phi workgroup at these line lengths),
+    # whatever the tuner picked for the step, so that the roofline kernel's
+    # launch is the same in every run and in the profiler runs
+    kplan = Plan(R, T, P, F, parity=w.parity, L=w.L, rho=w.rho)
+    ms_theta = time_loop(torch, lambda b: kplan.apply_theta(b, out=b), bufs, args.steps, 2, stream)
+    ms_phi = time_loop(torch, lambda b: kplan.apply_phi(b, out=b), bufs, args.steps, 2, stream)
+    kplan.close()
     th_bytes = 16 * st["theta_shells_active"] * T * P
     ph_bytes = 16 * st["phi_rings_active"] * P
     if ms_phi >= ms_theta:

@@ -201,6 +201,12 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[NV], int t, int ka, in
     const int m = c >= (double)N ? N : (int)floor(c);
     const double g_exp = exp((c - (double)m) - 1.0) * inv_n;
     const double inv_c1 = 1.0 / (c + 1.0);
+    // Each real line's kind as 0/1 weights, so that the per-mode factors are
+    // blends rather than branches (a select chain on the kind was lowered to
+    // a switch per mode: hundreds of divergent branches per workgroup).
+    // Weights of 1 and 0 keep the blends exact.
+    const double ga = ka == 1 ? 1.0 : 0.0, ea = ka == 0 ? 1.0 : 0.0, sa = ka == 2 ? 1.0 : 0.0;
+    const double gb = kb == 1 ? 1.0 : 0.0, eb = kb == 0 ? 1.0 : 0.0, sb = kb == 2 ? 1.0 : 0.0;
     static_for<0, R>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
         if constexpr (PAD) {
@@ -226,9 +232,12 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[NV], int t, int ka, in
             // one Gaussian factor per mode, shared by both kinds
             const double u = (double)qhat * inv_c1;
             const double fg = exp(kLog09 * u * u) * inv_n;
-            const double tail = qhat <= m ? inv_n : g_exp * etab[qhat > m ? qhat - m - 1 : 0];
-            const double fa = ka == 1 ? fg : (ka == 0 || qhat <= m ? tail : 0.0);
-            const double fb = kb == 1 ? fg : (kb == 0 || qhat <= m ? tail : 0.0);
+            const double e = etab[max(qhat - m - 1, 0)];
+            const bool below = qhat <= m;
+            const double tail = below ? inv_n : g_exp * e;     // exponential
+            const double keep = below ? inv_n : 0.0;           // sharp
+            const double fa = ga * fg + ea * tail + sa * keep;
+            const double fb = gb * fg + eb * tail + sb * keep;
             const double alpha = 0.5 * (fa + fb), beta = 0.5 * (fa - fb);
             const int qp = (N - q) % N;
             v[r * N2 + k2].re = alpha * v[r * N2 + k2].re + beta * P[qp];
@@ -375,13 +384,23 @@ __device__ __forceinline__ void filter_line(cplx (&v)[NV], int t, int kind, int 
     }
 
     // inverse: N2-point inverse DFTs, conjugate twiddles W_N^{-n2 k1},
-    // transpose back, N1-point inverse DFTs
+    // transpose back, N1-point inverse DFTs.  In the hybrid-capable variant
+    // the table address takes an opaque zero offset here, so that the
+    // inverse twiddles are not loaded before the two-kind mask and held
+    // across it (that pushed the register count past the two-wave limit and
+    // spilled 16-40 registers at N = 256).
+    const Twiddle *tw_inv = tw;
+    if constexpr (HYB) {
+        int zero = 0;
+        asm volatile("" : "+v"(zero));
+        tw_inv = tw + zero;
+    }
     static_for<0, R>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
         dft_reg<N2, true, r * N2>(v);
         // a padded row's twiddles stay inside the table (its result is dropped)
         const int k1 = t + N2 * r;
-        twiddle_powers<N2, true, r * N2>(v, tw, PAD && k1 >= N1 ? 0 : k1);
+        twiddle_powers<N2, true, r * N2>(v, tw_inv, PAD && k1 >= N1 ? 0 : k1);
     });
     transpose_bwd<N1, N2>(v, t, L);
     dft_reg<N1, true>(v);

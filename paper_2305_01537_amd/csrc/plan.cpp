@@ -376,6 +376,31 @@ int time_plan(sphfilt_plan p, double *x, hipStream_t s, int reps, double *us)
     return SPHFILT_OK;
 }
 
+// Run forward filters until the GPU has spent >= 25 ms on them.
+int warm_plan(sphfilt_plan p, double *x, hipStream_t s)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SPHFILT_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SPHFILT_EDEVICE; }
+    int rc = SPHFILT_OK;
+    float spent = 0.0f;
+    for (int k = 0; k < 256 && spent < 25.0f && !rc; ++k) {
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = SPHFILT_EDEVICE; break; }
+        for (int i = 0; i < 8 && !rc; ++i) rc = apply_two(p, Pass::Theta, Pass::Phi, x, x, Decisions{}, s);
+        if (rc) break;
+        float ms = 0;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = SPHFILT_EDEVICE;
+            break;
+        }
+        spent += ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 // Coordinate descent from the plan's current schedule over the theta tile
 // width, the ring pairs per phi workgroup, fused shells (where the grid has
 // them), the theta variant (where the circulant product applies) and the
@@ -401,7 +426,7 @@ int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
         tried.push_back(c);
         set_plan_sched(p, c);
         double us = 0;
-        rc = time_plan(p, x, s, 5, &us);
+        rc = time_plan(p, x, s, 9, &us);
         if (rc) return;
         if (default_us < 0) default_us = us;
         if (us < best_us) {
@@ -409,6 +434,10 @@ int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
             best = c;
         }
     };
+    // Warm the GPU up first (its clock needs ~10 ms of continuous work; timed
+    // cold, the first candidates would read slow and the order of the search
+    // would decide the pick).
+    if (!rc) rc = warm_plan(p, x, s);
     try_sched(start);
     const int nl = 2 * p->n_theta;
     for (int w : {4, 8, 16, 32, 64})
@@ -441,6 +470,30 @@ int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
             c.overlap = o;
             try_sched(c);
         }
+    // confirm: the pick against the starting settings, three alternating
+    // rounds each; keep the pick only if it is faster by more than 1 %
+    if (!rc && !(best == start)) {
+        std::vector<double> tb, ts;
+        for (int round = 0; round < 3 && !rc; ++round) {
+            double us = 0;
+            set_plan_sched(p, best);
+            rc = time_plan(p, x, s, 5, &us);
+            tb.push_back(us);
+            set_plan_sched(p, start);
+            if (!rc) rc = time_plan(p, x, s, 5, &us);
+            ts.push_back(us);
+        }
+        if (!rc) {
+            std::sort(tb.begin(), tb.end());
+            std::sort(ts.begin(), ts.end());
+            best_us = tb[1];
+            default_us = ts[1];
+            if (!(tb[1] < 0.99 * ts[1])) {
+                best = start;
+                best_us = ts[1];
+            }
+        }
+    }
     if (s) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
