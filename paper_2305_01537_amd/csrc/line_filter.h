@@ -126,6 +126,50 @@ __device__ __forceinline__ void st_two(double *row, int kr, int ki, double re, d
     }
 }
 
+// Gaussian factors of one second-stage row, with the 1/N folded in.  The
+// row holds the modes q = q0 + N1 k2, k2 < N2 (q0 = t + N2 r < N1), whose
+// folded indices |q| run along two arithmetic sequences of step N1:
+//   k2 <  N2/2:  |q| = q0 + N1 k2,
+//   k2 >= N2/2:  |q| = N - q = (N1 - q0) + N1 j,  j = N2 - 1 - k2.
+// Along |q| = b + N1 j, with kappa = log(0.9) / (c + 1)^2, consecutive
+// factors exp(kappa |q|^2) have the ratio g_j = exp(kappa N1 (2b + N1 (2j + 1))),
+// and g_{j+1} = g_j exp(2 kappa N1^2): two exps per sequence and one per line
+// instead of one per mode.  The j-th factor carries about j^2 / 2 roundings
+// more than a direct exp (below 1e-14 relative for j < 8).  gauss_factors
+// writes the factor of mode k2 to f[k2].
+template <int N1>
+struct GaussChain {
+    double kappa, step;     // log(0.9) / (c + 1)^2, exp(2 kappa N1^2)
+    __device__ __forceinline__ explicit GaussChain(double c)
+    {
+        const double inv = 1.0 / (c + 1.0);
+        kappa = kLog09 * inv * inv;
+        step = exp(2.0 * kappa * (double)(N1 * N1));
+    }
+};
+
+template <int N1, int N2>
+__device__ __forceinline__ void gauss_factors(int q0, const GaussChain<N1> &g, double (&f)[N2])
+{
+    constexpr double inv_n = 1.0 / (N1 * N2);
+    constexpr double D = N1;
+    static_assert(N2 % 2 == 0, "two sequences of N2 / 2 modes");
+    static_for<0, 2>([&](auto hh) {
+        constexpr int h = decltype(hh)::value;
+        const double b = h == 0 ? (double)q0 : (double)(N1 - q0);
+        double fj = exp(g.kappa * b * b) * inv_n;
+        double ratio = exp(g.kappa * D * (2.0 * b + D));
+        static_for<0, N2 / 2>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            f[h == 0 ? j : N2 - 1 - j] = fj;
+            if constexpr (j + 1 < N2 / 2) {
+                fj *= ratio;
+                ratio *= g.step;
+            }
+        });
+    });
+}
+
 // Mask of one line, with the inverse transform's 1/N folded in.  v holds
 // X[q] at q = t + N2 r + N1 k2 in v[r N2 + k2].
 //   exponential (eq. exp_filter): f = 1 for |q| <= c, else exp(-(|q| - c)).
@@ -133,7 +177,8 @@ __device__ __forceinline__ void st_two(double *row, int kr, int ki, double re, d
 //     exp(c - |q|) = exp(c - m - 1) * e^{-(|q| - m - 1)}: one exp per lane and
 //     a table of e^{-k}, instead of one exp per mode.
 //   sharp: the same with the factor above the cutoff set to 0.
-//   Gaussian (eq. gaussian_filter): f = exp(log(0.9) (|q| / (c + 1))^2).
+//   Gaussian (eq. gaussian_filter): f = exp(log(0.9) (|q| / (c + 1))^2),
+//     formed along the row by gauss_factors.
 template <int N1, int N2, int NV>
 __device__ __forceinline__ void apply_mask(cplx (&v)[NV], int t, int kind, double c,
                                            const double *etab)
@@ -143,19 +188,18 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[NV], int t, int kind, doubl
     constexpr bool PAD = NV != N1;        // padded second stage: rows k1 >= N1 are empty
     constexpr double inv_n = 1.0 / N;
     if (kind == 1) {
-        const double inv = 1.0 / (c + 1.0);
+        const GaussChain<N1> g(c);
         static_for<0, R>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
             if constexpr (PAD) {
                 if (t + N2 * r >= N1) return;
             }
+            double f[N2];
+            gauss_factors<N1, N2>(t + N2 * r, g, f);
             static_for<0, N2>([&](auto kk) {
                 constexpr int k2 = decltype(kk)::value;
-                const int q = t + N2 * r + N1 * k2;
-                const double u = (double)(q <= N / 2 ? q : N - q) * inv;
-                const double f = exp(kLog09 * u * u) * inv_n;
-                v[r * N2 + k2].re *= f;
-                v[r * N2 + k2].im *= f;
+                v[r * N2 + k2].re *= f[k2];
+                v[r * N2 + k2].im *= f[k2];
             });
         });
     } else {
@@ -178,6 +222,27 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[NV], int t, int kind, doubl
     }
 }
 
+// Ordering of LDS accesses among the lanes of one wave: lanes of a wave see
+// each other's earlier LDS writes (a wave's LDS instructions complete in
+// order); the fences keep the compiler from moving accesses across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Synchronise the lanes of a line: a workgroup barrier, or, where the line's
+// lanes all lie in one wave (WAVE: the phi layout), the wave-level ordering.
+template <bool WAVE>
+__device__ __forceinline__ void line_sync()
+{
+    if constexpr (WAVE)
+        wave_lds_sync();
+    else
+        __syncthreads();
+}
+
 // Mask of a complex line whose two real lines take different kinds (the
 // hybrid filter can pick the Gaussian for one and the exponential for the
 // other).  With z = a + i b and Z its transform, A and B (the transforms of a
@@ -185,12 +250,12 @@ __device__ __forceinline__ void apply_mask(cplx (&v)[NV], int t, int kind, doubl
 //   f_a A + i f_b B = (f_a + f_b)/2 Z[q] + (f_a - f_b)/2 conj Z[N - q].
 // Bin N - q lives on another lane: every lane publishes its bins through the
 // line's LDS region P (2N doubles: real parts, then imaginary parts, natural
-// order), so one barrier serves both parts and each mode's factors are used
-// as soon as they are formed.  Lines with ka == kb get plain f Z.  All lanes
-// of the workgroup call this together.  (Restricting the exchange to the
-// lines that mix two kinds saves nothing in the theta pass: one theta wave
-// holds lanes of every line of the workgroup, so its waves run both paths.)
-template <int N1, int N2, int NV>
+// order), so one synchronisation serves both parts.  Lines with ka == kb get
+// plain f Z.  All lanes of the workgroup (WAVE: of the wave) call this
+// together.  (In the theta layout one wave holds lanes of every line of the
+// workgroup, so restricting the exchange to the lines that mix two kinds
+// would save nothing there.)
+template <int N1, int N2, bool WAVE, int NV>
 __device__ __forceinline__ void apply_mask_pair(cplx (&v)[NV], int t, int ka, int kb, double c,
                                                 const double *etab, double *P)
 {
@@ -200,7 +265,7 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[NV], int t, int ka, in
     constexpr double inv_n = 1.0 / N;
     const int m = c >= (double)N ? N : (int)floor(c);
     const double g_exp = exp((c - (double)m) - 1.0) * inv_n;
-    const double inv_c1 = 1.0 / (c + 1.0);
+    const GaussChain<N1> gc(c);
     // Each real line's kind as 0/1 weights, so that the per-mode factors are
     // blends rather than branches (a select chain on the kind was lowered to
     // a switch per mode: hundreds of divergent branches per workgroup).
@@ -219,19 +284,19 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[NV], int t, int ka, in
             P[N + q] = v[r * N2 + k2].im;
         });
     });
-    __syncthreads();
+    line_sync<WAVE>();
     static_for<0, R>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
         if constexpr (PAD) {
             if (t + N2 * r >= N1) return;
         }
+        double fgs[N2];
+        gauss_factors<N1, N2>(t + N2 * r, gc, fgs);
         static_for<0, N2>([&](auto kk) {
             constexpr int k2 = decltype(kk)::value;
+            const double fg = fgs[k2];
             const int q = t + N2 * r + N1 * k2;
             const int qhat = q <= N / 2 ? q : N - q;
-            // one Gaussian factor per mode, shared by both kinds
-            const double u = (double)qhat * inv_c1;
-            const double fg = exp(kLog09 * u * u) * inv_n;
             const double e = etab[max(qhat - m - 1, 0)];
             const bool below = qhat <= m;
             const double tail = below ? inv_n : g_exp * e;     // exponential
@@ -244,7 +309,7 @@ __device__ __forceinline__ void apply_mask_pair(cplx (&v)[NV], int t, int ka, in
             v[r * N2 + k2].im = alpha * v[r * N2 + k2].im - beta * P[N + qp];
         });
     });
-    __syncthreads();
+    line_sync<WAVE>();
 }
 
 // LDS doubles per line: an N1 x (N2 + 1) padded tile plus one double, so that
@@ -353,7 +418,9 @@ __device__ __forceinline__ void twiddle_powers(cplx (&v)[NV], const Twiddle *__r
 // holds x[N2 n1 + t] in v[n1]); on return v holds the filtered values at the
 // same positions.  Every lane of the workgroup calls this together.
 // etab: e^{-k}, k <= N/2, in LDS, written before the first barrier here.
-template <int N1, int N2, bool HYB, int NV>
+// WAVE (hybrid-capable variant): the line's lanes lie in one wave and
+// `mixed` is wave-uniform, so the two-kind mask synchronises the wave only.
+template <int N1, int N2, bool HYB, bool WAVE = false, int NV>
 __device__ __forceinline__ void filter_line(cplx (&v)[NV], int t, int kind, int kind_b, bool mixed,
                                             double c, double *L, const Twiddle *__restrict__ tw,
                                             const double *etab)
@@ -372,11 +439,12 @@ __device__ __forceinline__ void filter_line(cplx (&v)[NV], int t, int kind, int 
     static_for<0, R>([&](auto rr) { dft_reg<N2, false, decltype(rr)::value * N2>(v); });
 
     // kind: the real part's filter; kind_b: the imaginary part's.  mixed
-    // (workgroup-uniform) is set when some line of the workgroup has two;
-    // only the hybrid-capable variant (HYB) carries that code.
+    // (workgroup-uniform, or wave-uniform with WAVE) is set when some line of
+    // the workgroup (wave) has two; only the hybrid-capable variant (HYB)
+    // carries that code.
     if constexpr (HYB) {
         if (mixed)
-            apply_mask_pair<N1, N2>(v, t, kind, kind_b, c, etab, L);
+            apply_mask_pair<N1, N2, WAVE>(v, t, kind, kind_b, c, etab, L);
         else
             apply_mask<N1, N2>(v, t, kind, c, etab);
     } else {
@@ -440,51 +508,118 @@ template <> struct Split<192> : SplitOf<12, 16> {};
 template <> struct Split<256> : SplitOf<16, 16> {};
 
 
+// One cell of Jameson's detector: sigma = num / den >= threshold (threshold
+// > 0), decided as the rounded quotient decides it, mostly without the
+// division.  r = num - threshold den is formed with one rounding (fma), so its
+// sign is that of the exact difference: r > 0 means num / den > threshold, so
+// the rounded quotient is >= threshold (fires); r below -2^-50 threshold den
+// (plus a floor for tiny values) puts the exact quotient more than an ulp
+// below the threshold, so the rounded one stays below (does not fire).  The
+// rest (r near zero, den zero, non-finite values) is `unsure`: the caller
+// decides those cells by the division itself.
+struct JamesonCell {
+    bool fires, unsure;
+};
+
+__device__ __forceinline__ double jameson_num(double a, double b, double c)
+{
+    return fabs(a - 2.0 * b + c);
+}
+
+__device__ __forceinline__ double jameson_den(double a, double b, double c, double eps)
+{
+    return fabs(a) + 2.0 * fabs(b) + fabs(c) + eps;
+}
+
+__device__ __forceinline__ JamesonCell jameson_cell(double a, double b, double c, double eps,
+                                                    double threshold)
+{
+    const double num = jameson_num(a, b, c), den = jameson_den(a, b, c, eps);
+    const double r = fma(-threshold, den, num);
+    const double margin = fma(threshold * 0x1p-50, den, 0x1p-1000);
+    return JamesonCell{r > 0.0, !(r > 0.0) && !(r < -margin)};
+}
+
 // Jameson's detector sigma_i = |u_{i-1} - 2u_i + u_{i+1}| /
 // (|u_{i-1}| + 2|u_i| + |u_{i+1}| + eps) on the two real lines packed in v
 // (periodic along the line).  Returns bit 0 if any cell of the real-part
 // line has sigma >= threshold, bit 1 for the imaginary-part line.  Lanes
 // publish both real lines through the line's LDS region L (2N doubles: the
-// hybrid-capable kernels' line stride) and combine their findings in *flag
-// (this line's LDS word).  All lanes call this together; `check` says whether
-// this lane's line needs the detector at all.
-template <int N1, int N2, int NV>
+// hybrid-capable kernels' line stride) to read their neighbours, and combine
+// their findings in *flag (this line's LDS word) behind workgroup barriers;
+// with WAVE (the line's N2 lanes are consecutive lanes of one wave, aligned to
+// N2) a wave-level ordering and a ballot do instead.  All lanes of the
+// workgroup call this together; `check` says whether this lane's line needs
+// the detector at all.
+template <int N1, int N2, bool WAVE, int NV>
 __device__ __forceinline__ int detect_shocks(const cplx (&v)[NV], int t, double *L, int *flag,
                                              bool check, double eps, double threshold)
 {
     constexpr int N = N1 * N2;
-    if (t == 0) *flag = 0;
+    if constexpr (!WAVE) {
+        if (t == 0) *flag = 0;
+    }
     static_for<0, N1>([&](auto nn) {
         constexpr int n1 = decltype(nn)::value;
         L[N2 * n1 + t] = v[n1].re;
         L[N + N2 * n1 + t] = v[n1].im;
     });
-    __syncthreads();
+    line_sync<WAVE>();
     int bits = 0;
     if (check) {
+        // straight-line sign tests over every cell of the lane; the cells they
+        // leave unsure (never, with random data) go through the division in a
+        // second, rarely entered loop
+        int unsure = 0;
         static_for<0, 2>([&](auto part) {
-            constexpr bool im = decltype(part)::value == 1;
-            const double *Lp = L + (im ? N : 0);
+            constexpr int im = decltype(part)::value;
+            const double *Lp = L + im * N;
             static_for<0, N1>([&](auto nn) {
                 constexpr int n1 = decltype(nn)::value;
                 const int n = N2 * n1 + t;
-                const double a = Lp[(n + N - 1) % N];
                 const double b = im ? v[n1].im : v[n1].re;
-                const double c = Lp[(n + 1) % N];
-                const double sigma = fabs(a - 2.0 * b + c) / (fabs(a) + 2.0 * fabs(b) + fabs(c) + eps);
-                if (sigma >= threshold) bits |= im ? 2 : 1;
+                const JamesonCell cell = jameson_cell(Lp[(n + N - 1) % N], b, Lp[(n + 1) % N], eps,
+                                                      threshold);
+                bits |= cell.fires ? 1 << im : 0;
+                unsure |= cell.unsure ? 1 << im : 0;
             });
         });
+        if (unsure) {
+            static_for<0, 2>([&](auto part) {
+                constexpr int im = decltype(part)::value;
+                const double *Lp = L + im * N;
+                static_for<0, N1>([&](auto nn) {
+                    constexpr int n1 = decltype(nn)::value;
+                    const int n = N2 * n1 + t;
+                    const double a = Lp[(n + N - 1) % N], c = Lp[(n + 1) % N];
+                    const double b = im ? v[n1].im : v[n1].re;
+                    if ((unsure >> im) & 1)
+                        bits |= jameson_num(a, b, c) / jameson_den(a, b, c, eps) >= threshold ? 1 << im : 0;
+                });
+            });
+        }
     }
-    if (bits) atomicOr(flag, bits);
-    __syncthreads();
-    return *flag;
+    if constexpr (WAVE) {
+        static_assert(64 % N2 == 0, "a line's lanes lie in one wave");
+        const unsigned long long re = __ballot((bits & 1) != 0), im = __ballot((bits & 2) != 0);
+        const int first = (int)__lane_id() & ~(N2 - 1);
+        const unsigned long long mine = (N2 == 64 ? ~0ull : ((1ull << N2) - 1)) << first;
+        // the region L is rewritten next (the transposes): keep this wave's
+        // neighbour reads ahead of that
+        wave_lds_sync();
+        return ((re & mine) ? 1 : 0) | ((im & mine) ? 2 : 0);
+    } else {
+        if (bits) atomicOr(flag, bits);
+        __syncthreads();
+        return *flag;
+    }
 }
 
 // The two kinds of a packed line: a hybrid line takes the Gaussian where its
 // detector fired (or its recorded decision says so), else the exponential.
-// dec_a / dec_b: byte offsets of the two real lines in h.dec.
-template <int N1, int N2, int NV>
+// dec_a / dec_b: byte offsets of the two real lines in h.dec.  *mixed is
+// workgroup-uniform, or with WAVE wave-uniform (see detect_shocks).
+template <int N1, int N2, bool WAVE, int NV>
 __device__ __forceinline__ void hybrid_kinds(const cplx (&v)[NV], int t, double *L, int *flag,
                                              bool active, int kind, size_t dec_a, size_t dec_b,
                                              const HybridArgs &h, int *ka, int *kb, bool *mixed)
@@ -498,7 +633,7 @@ __device__ __forceinline__ void hybrid_kinds(const cplx (&v)[NV], int t, double 
     if (h.replay) {
         if (hybrid) bits = (h.dec[dec_a] ? 1 : 0) | (h.dec[dec_b] ? 2 : 0);
     } else {
-        bits = detect_shocks<N1, N2>(v, t, L, flag, hybrid, h.eps, h.threshold);
+        bits = detect_shocks<N1, N2, WAVE>(v, t, L, flag, hybrid, h.eps, h.threshold);
         if (hybrid && h.dec && t == 0) {
             h.dec[dec_a] = (unsigned char)(bits & 1);
             h.dec[dec_b] = (unsigned char)((bits >> 1) & 1);
@@ -508,7 +643,10 @@ __device__ __forceinline__ void hybrid_kinds(const cplx (&v)[NV], int t, double 
         *ka = (bits & 1) ? 1 : 0;
         *kb = (bits & 2) ? 1 : 0;
     }
-    *mixed = __syncthreads_or(*ka != *kb) != 0;
+    if constexpr (WAVE)
+        *mixed = __ballot(*ka != *kb) != 0;
+    else
+        *mixed = __syncthreads_or(*ka != *kb) != 0;
 }
 
 // Lanes per line and lines per 256-lane workgroup for each supported N.
@@ -586,8 +724,8 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
         int ka = it.flags & kKindMask, kb = ka;
         bool mixed = false;
         if constexpr (HYB)
-            hybrid_kinds<N1, N2>(v, t, L, flags + p, active, ka, dline + kr, dline + ki, h, &ka,
-                                 &kb, &mixed);
+            hybrid_kinds<N1, N2, false>(v, t, L, flags + p, active, ka, dline + kr, dline + ki, h,
+                                        &ka, &kb, &mixed);
         filter_line<N1, N2, HYB>(v, t, ka, kb, mixed, active ? it.c : INFINITY, L, tw, etab);
     }
     if (valid && (active || !any_active)) {
@@ -650,9 +788,9 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
         int ka = it.flags & kKindMask, kb = ka;
         bool mixed = false;
         if constexpr (HYB)
-            hybrid_kinds<N1, N2>(v, t, L, flags + p, active, ka, (size_t)it.ring, ring_b, h, &ka,
-                                 &kb, &mixed);
-        filter_line<N1, N2, HYB>(v, t, ka, kb, mixed, active ? it.c : INFINITY, L, tw, etab);
+            hybrid_kinds<N1, N2, true>(v, t, L, flags + p, active, ka, (size_t)it.ring, ring_b, h,
+                                       &ka, &kb, &mixed);
+        filter_line<N1, N2, HYB, true>(v, t, ka, kb, mixed, active ? it.c : INFINITY, L, tw, etab);
     }
     if (valid && (active || !any_active)) {
         static_for<0, N1>([&](auto nn) {
@@ -861,7 +999,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         bool mixed = false;
         if constexpr (HYB) {
             const size_t dline = (size_t)it.shell * (size_t)(N / 2);
-            hybrid_kinds<N1, N2>(v, tt, L, flags + pt, valid_t, ka, dline + kr,
+            hybrid_kinds<N1, N2, false>(v, tt, L, flags + pt, valid_t, ka, dline + kr,
                                  dline + kr + S::lines, ht, &ka, &kb, &mixed);
         }
         filter_line<N1, N2, HYB>(v, tt, ka, kb, mixed, valid_t ? it.c : INFINITY, L, tw, etab);
@@ -872,10 +1010,10 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         bool mixed = false;
         if constexpr (HYB) {
             const size_t ring = (size_t)shell_p * (size_t)(N / 2) + j;
-            hybrid_kinds<N1, N2>(v, tp, L, flags + pp, valid_p, ka, ring,
+            hybrid_kinds<N1, N2, true>(v, tp, L, flags + pp, valid_p, ka, ring,
                                  ring + (size_t)(N / 2 - 1 - 2 * j), hp, &ka, &kb, &mixed);
         }
-        filter_line<N1, N2, HYB>(v, tp, ka, kb, mixed, c_p, L, tw, etab);
+        filter_line<N1, N2, HYB, true>(v, tp, ka, kb, mixed, c_p, L, tw, etab);
     };
 
     // the theta pass on the staged shells, ending with their contents updated

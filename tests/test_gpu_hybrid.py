@@ -240,3 +240,35 @@ def test_detector_decisions_at_the_threshold(torch_gpu):
     assert np.array_equal(got, ref)
     assert 0 < int(ref.sum()) < T          # both outcomes occur
     plan.close()
+
+
+def test_detector_theta_decisions_at_the_threshold(torch_gpu):
+    """The same steps along the meridians: meridian pair k carries a step of
+    height J_k from row T/2 on, so its extended theta line has largest sigma
+    J_k / (4 + J_k + eps) (the mirrored meridian is flat).  Decisions equal the
+    oracle's on both sides of the threshold."""
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Plan
+    T, P = 32, 32
+    J = [76.0, np.nextafter(76.0, 0.0), np.nextafter(76.0, 100.0), 76.0 * (1 - 1e-15),
+         76.0 * (1 + 1e-15), 76.0 * (1 - 3e-13), 76.0 * (1 + 3e-13), 75.9,
+         76.1, 70.0, 80.0, 76.0, 50.0, 120.0, 76.0 * (1 - 1e-14), 76.0 * (1 + 1e-14)]
+    x = np.ones((1, 1, T, P))
+    for k, jj in enumerate(J):
+        x[0, 0, T // 2:, k] = 1.0 + jj
+    eps = 1e-300
+    plan = Plan(1, T, P, 1, parity=[1], L=[0.5], kind=[HYBRID], detector_eps=eps)
+    th, ph = plan.decision_buffers()
+    plan.apply_ex(torch.from_numpy(x).cuda(), theta_dec=th, phi_dec=ph)
+    torch.cuda.synchronize()
+    try:
+        oracle.set_detector(eps, 0.95)
+        ref_th, _ = oracle.decisions(x, parity=np.array([1]), kind=np.array([HYBRID]))
+    finally:
+        oracle.set_detector()
+    got = th.cpu().numpy()
+    print(f"[gpu] theta threshold decisions gpu {got.ravel().tolist()} oracle {ref_th.ravel().tolist()}",
+          flush=True)
+    assert np.array_equal(got, ref_th)
+    assert 0 < int(ref_th.sum()) < P // 2  # both outcomes occur
+    plan.close()
