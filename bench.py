@@ -104,6 +104,9 @@ def parse():
     ap.add_argument("--mixed-radix-only", action="store_true",
                     help="time only the 96 x 192 and 80 x 160 grids (lines with a radix-3 or "
                          "radix-5 stage)")
+    ap.add_argument("--hybrid-only", action="store_true",
+                    help="time only the share with 8 hybrid fields and print its figures as JSON "
+                         "(for profiling the hybrid-capable kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=6.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -371,13 +374,23 @@ def bench_hybrid(torch, w, bufs, steps, stream):
     L = np.where(kind == 3, 12.0, 3.0)
     plan = Plan(R, T, P, F, parity=w.parity, L=L, rho=w.rho, kind=kind)
     st = plan.stats()
+    ms_default = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 3, stream)
+    # the plan's autotuner, as for the headline plan
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        tune = plan.tune(os.path.join(d, "tune.json"))
+    schedule = {"theta_cols": plan.get_schedule()[0], "phi_lines": plan.get_schedule()[1],
+                "overlap": plan.get_overlap(), **tune}
     ms = time_loop(torch, lambda b: plan.apply(b, out=b), bufs, steps, 3, stream)
+    ms_theta = time_loop(torch, lambda b: plan.apply_theta(b, out=b), bufs, steps, 2, stream)
+    ms_phi = time_loop(torch, lambda b: plan.apply_phi(b, out=b), bufs, steps, 2, stream)
     th, ph = plan.decision_buffers()
     ms_rec = time_loop(torch, lambda b: plan.apply_ex(b, out=b, theta_dec=th, phi_dec=ph), bufs,
                        steps, 3, stream)
     plan.close()
     return {"workload": "share, fields 0..7 hybrid (cal-L 12), 8..23 exponential (cal-L 3)",
-            "forward_ms": ms, "forward_recording_ms": ms_rec,
+            "forward_ms": ms, "forward_recording_ms": ms_rec, "forward_default_schedule_ms": ms_default,
+            "theta_pass_ms": ms_theta, "phi_pass_ms": ms_phi, "schedule": schedule,
             "points_per_s": st["n_points"] / (ms * 1e-3),
             "GBps": st["bytes_forward_inplace"] / (ms * 1e-3) / 1e9,
             "algorithmic_bytes": st["bytes_forward_inplace"]}
@@ -505,6 +518,11 @@ def main():
 
     log("generating the share workload (24 x 256 x 128 x 256, FP64)")
     w = synth.workload("share", L=args.L)
+    if args.hybrid_only:
+        x0 = torch.from_numpy(w.x).to(dev)
+        bufs = [x0] + [x0.clone() for _ in range(3)]
+        print(json.dumps({"hybrid": bench_hybrid(torch, w, bufs, args.steps, stream)}), flush=True)
+        return 0
     F, R, T, P = w.shape
     plan = Plan(R, T, P, F, parity=w.parity, L=w.L, rho=w.rho)
     st = plan.stats()

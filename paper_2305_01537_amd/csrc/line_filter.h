@@ -617,12 +617,16 @@ __device__ __forceinline__ int detect_shocks(const cplx (&v)[NV], int t, double 
 
 // The two kinds of a packed line: a hybrid line takes the Gaussian where its
 // detector fired (or its recorded decision says so), else the exponential.
-// dec_a / dec_b: byte offsets of the two real lines in h.dec.  *mixed is
-// workgroup-uniform, or with WAVE wave-uniform (see detect_shocks).
+// dec_a / dec_b: byte offsets of the two real lines in h.dec.  *mixed says
+// whether some line takes two kinds: over the wave with WAVE (see
+// detect_shocks), else over the workgroup, read from the n_lines flag words
+// flags[0, n_lines) (this line's is flags[line]), which hold each line's
+// detector bits (0 for lines that are not hybrid) after one barrier.
 template <int N1, int N2, bool WAVE, int NV>
-__device__ __forceinline__ void hybrid_kinds(const cplx (&v)[NV], int t, double *L, int *flag,
-                                             bool active, int kind, size_t dec_a, size_t dec_b,
-                                             const HybridArgs &h, int *ka, int *kb, bool *mixed)
+__device__ __forceinline__ void hybrid_kinds(const cplx (&v)[NV], int t, double *L, int *flags,
+                                             int line, int n_lines, bool active, int kind,
+                                             size_t dec_a, size_t dec_b, const HybridArgs &h,
+                                             int *ka, int *kb, bool *mixed)
 {
     *ka = kind;
     *kb = kind;
@@ -632,8 +636,12 @@ __device__ __forceinline__ void hybrid_kinds(const cplx (&v)[NV], int t, double 
     int bits = 0;
     if (h.replay) {
         if (hybrid) bits = (h.dec[dec_a] ? 1 : 0) | (h.dec[dec_b] ? 2 : 0);
+        if constexpr (!WAVE) {
+            if (t == 0) flags[line] = bits;
+            __syncthreads();
+        }
     } else {
-        bits = detect_shocks<N1, N2, WAVE>(v, t, L, flag, hybrid, h.eps, h.threshold);
+        bits = detect_shocks<N1, N2, WAVE>(v, t, L, flags + line, hybrid, h.eps, h.threshold);
         if (hybrid && h.dec && t == 0) {
             h.dec[dec_a] = (unsigned char)(bits & 1);
             h.dec[dec_b] = (unsigned char)((bits >> 1) & 1);
@@ -643,10 +651,17 @@ __device__ __forceinline__ void hybrid_kinds(const cplx (&v)[NV], int t, double 
         *ka = (bits & 1) ? 1 : 0;
         *kb = (bits & 2) ? 1 : 0;
     }
-    if constexpr (WAVE)
+    if constexpr (WAVE) {
         *mixed = __ballot(*ka != *kb) != 0;
-    else
-        *mixed = __syncthreads_or(*ka != *kb) != 0;
+    } else {
+        // a line takes two kinds exactly when one of its two bits is set
+        bool any = false;
+        for (int i = 0; i < n_lines; ++i) {
+            const int f = flags[i];
+            any |= f == 1 || f == 2;
+        }
+        *mixed = any;
+    }
 }
 
 // Lanes per line and lines per 256-lane workgroup for each supported N.
@@ -724,7 +739,7 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
         int ka = it.flags & kKindMask, kb = ka;
         bool mixed = false;
         if constexpr (HYB)
-            hybrid_kinds<N1, N2, false>(v, t, L, flags + p, active, ka, dline + kr, dline + ki, h,
+            hybrid_kinds<N1, N2, false>(v, t, L, flags, p, C, active, ka, dline + kr, dline + ki, h,
                                         &ka, &kb, &mixed);
         filter_line<N1, N2, HYB>(v, t, ka, kb, mixed, active ? it.c : INFINITY, L, tw, etab);
     }
@@ -788,8 +803,8 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
         int ka = it.flags & kKindMask, kb = ka;
         bool mixed = false;
         if constexpr (HYB)
-            hybrid_kinds<N1, N2, true>(v, t, L, flags + p, active, ka, (size_t)it.ring, ring_b, h,
-                                       &ka, &kb, &mixed);
+            hybrid_kinds<N1, N2, true>(v, t, L, flags, p, LINES, active, ka, (size_t)it.ring, ring_b,
+                                       h, &ka, &kb, &mixed);
         filter_line<N1, N2, HYB, true>(v, t, ka, kb, mixed, active ? it.c : INFINITY, L, tw, etab);
     }
     if (valid && (active || !any_active)) {
@@ -999,7 +1014,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         bool mixed = false;
         if constexpr (HYB) {
             const size_t dline = (size_t)it.shell * (size_t)(N / 2);
-            hybrid_kinds<N1, N2, false>(v, tt, L, flags + pt, valid_t, ka, dline + kr,
+            hybrid_kinds<N1, N2, false>(v, tt, L, flags, pt, C, valid_t, ka, dline + kr,
                                  dline + kr + S::lines, ht, &ka, &kb, &mixed);
         }
         filter_line<N1, N2, HYB>(v, tt, ka, kb, mixed, valid_t ? it.c : INFINITY, L, tw, etab);
@@ -1010,7 +1025,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         bool mixed = false;
         if constexpr (HYB) {
             const size_t ring = (size_t)shell_p * (size_t)(N / 2) + j;
-            hybrid_kinds<N1, N2, true>(v, tp, L, flags + pp, valid_p, ka, ring,
+            hybrid_kinds<N1, N2, true>(v, tp, L, flags, pp, C, valid_p, ka, ring,
                                  ring + (size_t)(N / 2 - 1 - 2 * j), hp, &ka, &kb, &mixed);
         }
         filter_line<N1, N2, HYB, true>(v, tp, ka, kb, mixed, c_p, L, tw, etab);
