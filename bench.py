@@ -96,6 +96,9 @@ def parse():
     ap.add_argument("--patches-only", action="store_true",
                     help="time only the 64-patch batch and print its figures as JSON "
                          "(for profiling the batch kernel)")
+    ap.add_argument("--batch-schedule", type=str, default=None,
+                    help="with --patches-only: split,workgroups_per_cu,theta_tiles,phi_groups "
+                         "set instead of the tuner's pick (for profiling one schedule)")
     ap.add_argument("--grmhd-only", action="store_true",
                     help="time only the grmhd grid, fused and two-pass, and print its figures "
                          "as JSON (for profiling the fused shell kernel)")
@@ -252,10 +255,12 @@ def calibrate_copy(torch, x, reps=3):
     return {"copy_bytes_each": 2 * x.numel() * 8, "reps": reps}
 
 
-def bench_patches(torch, steps, stream, n_theta_choices=(16, 32, 64, 128)):
+def bench_patches(torch, steps, stream, n_theta_choices=(16, 32, 64, 128), force=None):
     """64 uneven patches: one tuned graph-replayed batch launch against one plan
     (two kernel launches) per patch, forward in place, same buffers.
-    n_theta_choices: the patches' n_theta (n_phi = 2 n_theta)."""
+    n_theta_choices: the patches' n_theta (n_phi = 2 n_theta).  force: a
+    schedule (split, workgroups per CU, theta tiles, phi groups) set instead of
+    the tuner's; then only the batched forward is timed."""
     import tempfile
     from paper_2305_01537_amd import synth
     from paper_2305_01537_amd.filter import Batch, Plan
@@ -263,6 +268,19 @@ def bench_patches(torch, steps, stream, n_theta_choices=(16, 32, 64, 128)):
     g = torch.Generator(device="cuda").manual_seed(4)
     xs = [torch.randn((p.n_fields, p.n_r, p.n_theta, p.n_phi), dtype=torch.float64, device="cuda",
                       generator=g) for p in pts]
+    if force is not None:
+        batch = Batch(pts)
+        batch.set_schedule_ex(split=force[0], workgroups_per_cu=force[1], fused=True,
+                              theta_tiles=force[2], phi_groups=force[3])
+        st = batch.stats()
+        ms_b = time_loop(torch, lambda b: batch.apply(b, outs=b), [xs], steps, 3, stream)
+        assert batch.status() == 0
+        out = {"patches": len(pts), "algorithmic_bytes": st["bytes_fused_inplace"],
+               "batched_forward_ms": ms_b,
+               "batched_GBps": st["bytes_fused_inplace"] / (ms_b * 1e-3) / 1e9,
+               "schedule": batch.get_schedule()}
+        batch.close()
+        return out
     with tempfile.TemporaryDirectory() as d:
         batch = Batch(pts, tune_cache=os.path.join(d, "tune.json"))
     sched = batch.get_schedule()
@@ -504,7 +522,11 @@ def main():
     stream = torch.cuda.current_stream(dev)
     t_start = time.perf_counter()
     if args.patches_only:
-        print(json.dumps({"patches": bench_patches(torch, args.steps, stream)}), flush=True)
+        force = None
+        if args.batch_schedule:
+            force = tuple(int(v) for v in args.batch_schedule.split(","))
+            assert len(force) == 4, "--batch-schedule takes four integers"
+        print(json.dumps({"patches": bench_patches(torch, args.steps, stream, force=force)}), flush=True)
         return 0
     if args.grmhd_only:
         print(json.dumps({"grmhd": bench_grmhd(torch, args.steps, stream)}), flush=True)

@@ -28,6 +28,17 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-command-line-argument",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
+# The batch kernels loop over work items (and over tiles and ring groups
+# inside an item).  Machine-level loop-invariant code motion hoists the
+# constants of every exp() in the loop body out of those loops, keeps them
+# live across the whole item and spills them (the persistent plain kernel
+# reloaded them from scratch ~140 times per item; the hybrid one-shot kernel
+# spilled 83 registers).  Without that pass the batch kernels do not spill.
+# The plan kernels have no such loops and are built unchanged.
+PER_SOURCE_FLAGS = {s: ["-mllvm", "-disable-machine-licm"]
+                    for s in ("batch_plain.hip", "batch_hybrid.hip", "batch_mixed.hip",
+                              "batch_mixed_hybrid.hip")}
+
 
 def _jobs() -> int:
     try:
@@ -39,7 +50,8 @@ def _jobs() -> int:
 
 def _compile(src, extra, verbose):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", src, "-o", obj]
+    per = PER_SOURCE_FLAGS.get(os.path.basename(src), [])
+    cmd = [HIPCC, *FLAGS, *per, *extra, "-x", "hip", "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -56,14 +56,13 @@ static_assert(batch_lds_fits<32, false>() && batch_lds_fits<64, false>() &&
                   batch_lds_fits<96, true>() && batch_lds_fits<160, true>() &&
                   batch_lds_fits<192, true>(),
               "batch LDS holds every worker's line scratch");
-// Waves per SIMD the instances ask for.  One-shot: two for the hybrid forms
-// (a little over 256 registers: two waves with a small spill beat one) and
-// for the plain MIXED form.  Persistent: two for the plain power-of-two
-// form, one for the others.
+// Waves per SIMD the instances ask for (each then gets at most 256
+// registers).  One-shot: two.  Persistent: two for the plain forms, one for
+// the hybrid forms (about 270 registers: at two waves they would spill).
 template <bool HYB, bool MIXED>
 constexpr int oneshot_waves() { return 2; }
 template <bool HYB, bool MIXED>
-constexpr int persistent_waves() { return HYB || MIXED ? 1 : 2; }
+constexpr int persistent_waves() { return HYB ? 1 : 2; }
 
 // Hybrid lines in a batch decide from their data; decisions are not recorded.
 __device__ __forceinline__ HybridArgs batch_hybrid(const BatchPatchDev &pd)
@@ -256,22 +255,33 @@ __device__ __forceinline__ void flush_pending(const BatchArgs &a, int *pending, 
     __syncthreads();
 }
 
-// Take the next ticket (workgroup-uniform).
-__device__ __forceinline__ int next_ticket(int *ticket, int *cur)
+// Take the next `count` tickets (workgroup-uniform); returns the first.
+__device__ __forceinline__ int next_ticket(int *ticket, int *cur, int count = 1)
 {
-    if (threadIdx.x == 0) *cur = atomicAdd(ticket, 1);
+    if (threadIdx.x == 0) *cur = atomicAdd(ticket, count);
     __syncthreads();
     const int k = __builtin_amdgcn_readfirstlane(*cur);
     __syncthreads();
     return k;
 }
 
+// Tickets a persistent workgroup takes at once: every workgroup of the grid
+// takes from one counter, so each atomic queues behind the others' (the
+// counter serialises them); runs of up to kTicketRun items cut their number,
+// shrinking to single items for the last 2 x grid items so that the
+// workgroups still finish together.  `seen`: the last ticket value this
+// workgroup saw.
+constexpr int kTicketRun = 8;
+
+__device__ __forceinline__ int ticket_run(int seen, int n_work)
+{
+    const int left = n_work - seen, per = left / (2 * (int)gridDim.x);
+    return per < 1 ? 1 : per > kTicketRun ? kTicketRun : per;
+}
+
 // One-shot form: the grid has one workgroup per item.  With waits between
 // items a workgroup takes a ticket (so that every awaited item is held by a
 // running workgroup); without, it runs item blockIdx.x and saves the atomic.
-// The hybrid form needs a little more than 256 registers: two waves per SIMD
-// with a small spill (128 bytes per lane) beat one wave without (the hybrid
-// 64-patch batch: 2.05 against 2.64 ms).
 // MIXED: the instance that also takes lines of 48, 80, 96, 160 and 192 points,
 // launched only for batches that have such a patch, so that the power-of-two
 // instance keeps its code and register allocation.
@@ -289,9 +299,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(oneshot_wav
 // Persistent form: a fixed grid; each workgroup takes tickets until the list
 // is exhausted.  The lane index is re-read through an opaque move every item
 // so that per-lane index math is recomputed rather than kept live across
-// items (it would otherwise not fit in 256 registers).  The hybrid form, with
-// the detector and the mixed-pair mask, needs more than 256 registers; it runs
-// one wave per SIMD (at two it would spill 240 bytes per lane and lose a third).
+// items (it would otherwise not fit in 256 registers).
 template <bool HYB, bool MIXED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_waves<HYB, MIXED>()))) void batch_kernel_persistent(
     BatchArgs a)
@@ -302,21 +310,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_
     __shared__ int cur, gave_up;
     __shared__ int pending[kPendingItems], n_pending;
     if (threadIdx.x == 0) n_pending = 0;
+    int seen = 0;
     for (;;) {
-        const int k = next_ticket(a.ticket, &cur);
-        if (k >= a.n_work) break;
-        unsigned lane;
-        asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((unsigned)threadIdx.x));
-        if (a.defer) {
-            // signal what this workgroup finished before it may wait
-            const BatchWork &w = a.work[k];
-            if (w.second || n_pending == kPendingItems) flush_pending(a, pending, &n_pending, (int)lane);
-        }
-        run_item<HYB, MIXED>(a, k, (int)lane, lds, etab, flags, &gave_up);
-        if (a.defer && !a.work[k].second && a.work[k].n_shells > 0) {
-            __syncthreads();
-            if (lane == 0) pending[n_pending++] = k;
-            __syncthreads();
+        const int run = ticket_run(seen, a.n_work);
+        const int first = next_ticket(a.ticket, &cur, run);
+        if (first >= a.n_work) break;
+        seen = first + run;
+        const int last = min(seen, a.n_work);
+        // Items of a run go in ticket order: a run holds only tickets above
+        // those of runs taken before it, and waits point to lower tickets,
+        // so every chain of waits still ends.
+        for (int k = first; k < last; ++k) {
+            unsigned lane;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((unsigned)threadIdx.x));
+            if (a.defer) {
+                // signal what this workgroup finished before it may wait
+                const BatchWork &w = a.work[k];
+                if (w.second || n_pending == kPendingItems) flush_pending(a, pending, &n_pending, (int)lane);
+            }
+            run_item<HYB, MIXED>(a, k, (int)lane, lds, etab, flags, &gave_up);
+            if (a.defer && !a.work[k].second && a.work[k].n_shells > 0) {
+                __syncthreads();
+                if (lane == 0) pending[n_pending++] = k;
+                __syncthreads();
+            }
         }
     }
     if (a.defer) flush_pending(a, pending, &n_pending, (int)threadIdx.x);

@@ -1091,10 +1091,10 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
 
 namespace sphfilt {
 
-// The hybrid-capable theta and phi kernels need a little more than 256
-// registers at N = 256: two waves per SIMD with a small spill (68-84 bytes per
-// lane) beat one wave without (the share with 8 hybrid fields: 0.81 against
-// 1.25 ms per forward filter).
+// The hybrid-capable theta and phi kernels fit two waves per SIMD (at most
+// 256 registers) without spilling; two waves beat one by a wide margin (the
+// share with 8 hybrid fields ran 0.81 against 1.25 ms per forward filter
+// when the two-wave form still spilled a little).
 
 // Waves per SIMD a pass kernel asks the compiler for (it caps the registers
 // per lane at 512 / waves).  The hybrid-capable instances: two, where two
