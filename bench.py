@@ -405,9 +405,15 @@ def bench_hybrid(torch, w, bufs, steps, stream):
     th, ph = plan.decision_buffers()
     ms_rec = time_loop(torch, lambda b: plan.apply_ex(b, out=b, theta_dec=th, phi_dec=ph), bufs,
                        steps, 3, stream)
+    # the recorded decisions replayed (no detector), as the adjoint of the
+    # autograd backward runs them
+    plan.apply_ex(bufs[0], out=bufs[1], theta_dec=th, phi_dec=ph)
+    ms_rep = time_loop(torch, lambda b: plan.apply_ex(b, out=b, theta_dec=th, phi_dec=ph, replay=True),
+                       bufs, steps, 3, stream)
     plan.close()
     return {"workload": "share, fields 0..7 hybrid (cal-L 12), 8..23 exponential (cal-L 3)",
-            "forward_ms": ms, "forward_recording_ms": ms_rec, "forward_default_schedule_ms": ms_default,
+            "forward_ms": ms, "forward_recording_ms": ms_rec, "forward_replay_ms": ms_rep,
+            "forward_default_schedule_ms": ms_default,
             "theta_pass_ms": ms_theta, "phi_pass_ms": ms_phi, "schedule": schedule,
             "points_per_s": st["n_points"] / (ms * 1e-3),
             "GBps": st["bytes_forward_inplace"] / (ms * 1e-3) / 1e9,
