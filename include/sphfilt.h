@@ -238,8 +238,9 @@ int sphfilt_plan_get_fused(sphfilt_plan plan, int *enable, int *shells_fused);
  * Autotune a plan: the theta tile width and phi ring pairs per workgroup
  * (sphfilt_plan_set_schedule), fused shells, the theta variant and the
  * overlap mode, by coordinate descent from the plan's current settings, each
- * candidate timed as a forward filter in place on scratch fields of the
- * plan's size that the call allocates and frees.  The untuned settings are a
+ * candidate timed as forward filters in place, back to back (as a
+ * time-stepping loop calls them), on scratch fields of the plan's size that
+ * the call allocates and frees.  The untuned settings are a
  * candidate, so the pick is never slower than them by the tuner's own
  * measurement.
  *   tune_cache_path  a JSON file shared with the batch tuner: if it holds
@@ -250,7 +251,7 @@ int sphfilt_plan_get_fused(sphfilt_plan plan, int *enable, int *shells_fused);
  *                    by SPHFILT_TUNE_CACHE if set and not empty, else tune
  *                    without recording.
  * Synchronous; not thread-safe against concurrent calls on the same plan.
- * sphfilt_plan_tuned_times reports the tuner's time of one forward call with
+ * sphfilt_plan_tuned_times reports the tuner's time per forward call with
  * the pick and with the settings it started from (negative when not tuned;
  * NULL outputs are skipped).
  */
@@ -418,8 +419,8 @@ int sphfilt_batch_get_schedule(sphfilt_batch batch, int *split, int *workgroups_
 /*
  * The whole schedule of a batch, as the autotuner searches it (coordinate
  * descent from the untuned schedule, every candidate timed on scratch fields
- * with the batch's own kernels; the pick and both times are recorded in the
- * JSON cache):
+ * with the batch's own kernels, calls back to back; the pick and both times
+ * are recorded in the JSON cache):
  *   split, workgroups_per_cu  as for sphfilt_batch_set_schedule (get: the
  *                      effective workgroups per CU).
  *   fused              fused items (see sphfilt_batch_set_fused), 0 or 1.
@@ -432,7 +433,7 @@ int sphfilt_batch_get_schedule(sphfilt_batch batch, int *split, int *workgroups_
  *                      line has {32, 48, 64, 80, 96, 128, 160, 192, 256}[i]
  *                      points; 0 = the default width.  A width a patch's grid
  *                      does not take falls back to its default.
- *   tuned_us, default_us  (get only) the tuner's time of one call with the
+ *   tuned_us, default_us  (get only) the tuner's time per call with the
  *                      picked and with the untuned schedule; negative when
  *                      not tuned.
  * set_schedule_ex returns SPHFILT_EINVAL for values outside these sets;

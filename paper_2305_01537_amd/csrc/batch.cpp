@@ -486,7 +486,12 @@ int launch_noalloc(sphfilt_batch b, const double *const *ins, double *const *out
     return record(b, m, b->split, b->wpc, sc, fault("wait") ? 1 : 0, stream);
 }
 
-// Time the current schedule on scratch fields: median of `reps` graph launches.
+// Time the current schedule on scratch fields: the median over `reps` rounds
+// of the time per call, each round kBatchCallsPerRound graph launches back to
+// back, as a time-stepping loop makes them (one call at a time would expose
+// each launch's latency).
+constexpr int kBatchCallsPerRound = 3;
+
 int time_schedule(sphfilt_batch b, const std::vector<double *> &bufs, hipStream_t s, int reps, double *us)
 {
     std::vector<const double *> ins(bufs.begin(), bufs.end());
@@ -497,7 +502,7 @@ int time_schedule(sphfilt_batch b, const std::vector<double *> &bufs, hipStream_
     int rc = SPHFILT_OK;
     for (int r = 0; r < reps + 2 && !rc; ++r) {
         if (hipEventRecord(e0, s) != hipSuccess) { rc = SPHFILT_EDEVICE; break; }
-        rc = launch(b, ins.data(), bufs.data(), 0, s);
+        for (int c = 0; c < kBatchCallsPerRound && !rc; ++c) rc = launch(b, ins.data(), bufs.data(), 0, s);
         if (rc) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             rc = SPHFILT_EDEVICE;
@@ -505,7 +510,7 @@ int time_schedule(sphfilt_batch b, const std::vector<double *> &bufs, hipStream_
         }
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (r >= 2) t.push_back(ms);
+        if (r >= 2) t.push_back(ms / kBatchCallsPerRound);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -634,7 +639,7 @@ int warm_batch(sphfilt_batch b, const std::vector<double *> &bufs, hipStream_t s
         double us = 0;
         const int rc = time_schedule(b, bufs, s, 4, &us);
         if (rc) return rc;
-        spent += 6.0 * us;                     // time_schedule runs reps + 2 calls
+        spent += 6.0 * kBatchCallsPerRound * us;   // time_schedule runs reps + 2 rounds
     }
     return SPHFILT_OK;
 }
