@@ -593,6 +593,7 @@ def main():
         dom, dom_ms, dom_bytes, units = "theta_kernel", ms_theta, th_bytes, st["theta_shells_active"]
         unit_desc = f"{units} active shells x 128 x 256 points x 16 B"
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    step_gbps = st["bytes_forward_inplace"] / (ms_fwd * 1e-3) / 1e9
     log(f"theta {ms_theta:.4f} ms ({th_bytes / ms_theta / 1e6:.1f} GB/s), "
         f"phi {ms_phi:.4f} ms ({ph_bytes / ms_phi / 1e6:.1f} GB/s)")
 
@@ -600,7 +601,7 @@ def main():
         "plan_schedule": plan_schedule,
         "theta_pass_ms": ms_theta, "phi_pass_ms": ms_phi,
         "algorithmic_bytes_per_step": st["bytes_forward_inplace"],
-        "step_GBps": st["bytes_forward_inplace"] / (ms_fwd * 1e-3) / 1e9,
+        "step_GBps": step_gbps,
         "active_theta_shells": st["theta_shells_active"], "active_phi_rings": st["phi_rings_active"],
     }
     if not args.no_extra:
@@ -710,7 +711,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom, args.L),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": dom, "kernel_ms": dom_ms, "algorithmic_bytes": dom_bytes,
-                     "units": unit_desc},
+                     "units": unit_desc,
+                     # the whole step (both passes, overlapped) at ms_per_step
+                     "step_achieved": step_gbps, "step_frac": step_gbps / HBM_PEAK_GBS,
+                     "step_algorithmic_bytes": st["bytes_forward_inplace"]},
         "cpu_baseline": cpu,
         "extra": extra,
     }
