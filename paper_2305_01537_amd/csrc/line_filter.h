@@ -831,11 +831,11 @@ namespace sphfilt {
 // For n_phi = 2 n_theta = N a theta line and a phi ring have the same length
 // N, and a shell has as many complex theta lines (meridian pairs k and
 // k + N/4) as complex phi lines (ring pairs j and n_theta-1-j): N/4.  A
-// 256-lane workgroup takes `shells` whole shells: it stages them in LDS with
-// contiguous loads, filters them line by line in the theta layout, writes the
-// result back into the staged shells, filters them in the phi layout and
-// stores them with contiguous stores (the adjoint order runs the phi pass
-// first).  Lines are filtered as by theta_block and phi_block; a theta line
+// 256-lane workgroup takes `shells` whole shells: it loads their theta lines
+// from HBM, filters them, writes the result into a padded LDS copy of the
+// shells, reads it back in the phi layout, filters the rings and stores them
+// to HBM (the adjoint order runs the phi pass first).  Lines are filtered as
+// by theta_block and phi_block; a theta line
 // here packs meridian pairs k and k + N/4 (theta_block packs adjacent pairs at
 // these N), so the result is that of the two passes up to rounding.  The line
 // filter's LDS scratch reuses the staging memory.
@@ -951,6 +951,28 @@ __device__ __forceinline__ void shell_phi_io(cplx (&v)[Split<N>::N1], double *sb
     });
 }
 
+// The phi layout straight from / to HBM (the shell at `base`): line j packs
+// ring j and its mirror n_theta-1-j, whose rows are contiguous; a lane moves
+// x[N2 n1 + t] of both.  Invalid shells load zeros and store nothing.
+template <int N, bool LOAD>
+__device__ __forceinline__ void shell_phi_hbm(const double *in, double *out, size_t base,
+                                               cplx (&v)[Split<N>::N1], int t, int j, bool valid)
+{
+    constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+    constexpr bool cached = ring_loads_cached<N>();
+    const size_t a = base + (size_t)j * N + t, b = base + (size_t)(N / 2 - 1 - j) * N + t;
+    static_for<0, N1>([&](auto nn) {
+        constexpr int n1 = decltype(nn)::value;
+        if constexpr (LOAD) {
+            v[n1] = valid ? cplx{ld_piece<cached>(in + a + N2 * n1), ld_piece<cached>(in + b + N2 * n1)}
+                          : cplx{0.0, 0.0};
+        } else if (valid) {
+            st_stream<true>(out + a + N2 * n1, v[n1].re);
+            st_stream<true>(out + b + N2 * n1, v[n1].im);
+        }
+    });
+}
+
 // items: the workgroup's shells (n_valid of them); ring_c: their phi cutoffs,
 // lines per shell.  ht / hp: hybrid arguments of the theta and phi passes.
 // MFMA (plain kinds, N = 32 or 64 only): the theta pass is the circulant
@@ -977,12 +999,20 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
     constexpr size_t shell_pts = (size_t)N * N / 2;
     stage_exp_table<N>(etab, eneg, lane);
 
-    // Staging through LDS with contiguous HBM accesses is done on the phi
-    // side of the shell (the input of the adjoint order, the output of the
-    // forward order); the theta side loads or stores its lines straight in
-    // the theta layout (row segments, as the theta kernel does), saving one
-    // LDS round trip.  The circulant (MFMA) variant stages both sides.
-    constexpr bool theta_direct = !MFMA;
+    // The theta side of the shell moves straight between HBM and registers in
+    // the theta layout (row segments, as the theta kernel does).  At N = 128
+    // the phi side does too, in the phi layout (ring pieces of 64 bytes, as
+    // the phi kernel does), so LDS only carries the exchange between the two
+    // layouts (fused forward 448 -> 431 us on the dense n_phi = 128 grid,
+    // grmhd 34 -> 32 us); at N = 32 and 64 (ring pieces of 32 and 64 bytes)
+    // the phi side is staged through LDS with contiguous accesses, which
+    // measured as fast or faster.  The circulant (MFMA) variant stages whole
+    // shells on both sides.
+    constexpr bool theta_direct = !MFMA, phi_direct = !MFMA && N >= 128;
+    // the first pass's input and the last pass's output are staged with
+    // contiguous accesses unless that side moves directly
+    constexpr bool stage_in = ADJ ? !phi_direct : !theta_direct;
+    constexpr bool stage_out = ADJ ? !theta_direct : !phi_direct;
     const int us = lane / S::lanes;
     const bool valid_s = us < n_valid;
     const size_t base_s = valid_s ? (size_t)items[us].shell * shell_pts : 0;
@@ -996,7 +1026,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
     const size_t base_t = valid_t ? (size_t)it.shell * shell_pts : 0;
     double *sb_t = lds + ut * S::stride;
 
-    if (!(theta_direct && !ADJ)) {
+    if constexpr (stage_in) {
         shell_stage<N, true>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
         __syncthreads();
     }
@@ -1004,6 +1034,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
     const int tp = lane % N2, pp = lane / N2, up = pp / S::lines, j = pp % S::lines;
     const bool valid_p = up < n_valid;
     const int shell_p = valid_p ? items[up].shell : 0;
+    const size_t base_p = (size_t)shell_p * shell_pts;
     const int kind_p = valid_p ? (items[up].flags & kKindMask) : 0;
     const double c_p = valid_p ? ring_c[up * S::lines + j] : INFINITY;
     double *sb_p = lds + up * S::stride;
@@ -1072,16 +1103,23 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
         shell_phi_io<N, false>(v, sb_p, tp, j);
         __syncthreads();
         phi_filter();
-        shell_phi_io<N, true>(v, sb_p, tp, j);
+        if constexpr (phi_direct)
+            shell_phi_hbm<N, false>(in, out, base_p, v, tp, j, valid_p);
+        else
+            shell_phi_io<N, true>(v, sb_p, tp, j);
     } else {
-        shell_phi_io<N, false>(v, sb_p, tp, j);
-        __syncthreads();
+        if constexpr (phi_direct) {
+            shell_phi_hbm<N, true>(in, out, base_p, v, tp, j, valid_p);
+        } else {
+            shell_phi_io<N, false>(v, sb_p, tp, j);
+            __syncthreads();
+        }
         phi_filter();
         shell_phi_io<N, true>(v, sb_p, tp, j);
         __syncthreads();
         theta_pass();
     }
-    if (!(theta_direct && ADJ)) {
+    if constexpr (stage_out) {
         __syncthreads();
         shell_stage<N, false>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
     }
