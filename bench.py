@@ -609,16 +609,24 @@ def main():
         extra["adjoint_ms"] = ms_adj
         extra["adjoint_over_forward"] = ms_adj / ms_fwd
         log(f"adjoint {ms_adj:.4f} ms")
-        # the same forward with both passes on the caller's stream (no side stream)
+        # the same forward with the passes overlapped on a second stream (the
+        # rings of theta-idle shells alongside the theta pass), with the
+        # plan's phi launch shape and with full 256-lane phi workgroups
         mode = plan.get_overlap()
-        plan.set_overlap(0)
-        extra["forward_one_stream_ms"] = time_loop(torch, lambda b: plan.apply(b, out=b), bufs,
+        tc, pl = plan.get_schedule()
+        plan.set_overlap(1)
+        extra["forward_overlapped_ms"] = time_loop(torch, lambda b: plan.apply(b, out=b), bufs,
                                                    args.steps, 2, stream)
+        plan.set_schedule(phi_lines=16)
+        extra["forward_overlapped_phi16_ms"] = time_loop(torch, lambda b: plan.apply(b, out=b), bufs,
+                                                         args.steps, 2, stream)
+        plan.set_schedule(theta_cols=tc, phi_lines=pl)
         plan.set_overlap(mode)
         extra["forward_again_ms"] = time_loop(torch, lambda b: plan.apply(b, out=b), bufs,
                                               args.steps, 2, stream)
-        log(f"forward on one stream {extra['forward_one_stream_ms']:.4f} ms, "
-            f"again with overlap {extra['forward_again_ms']:.4f} ms")
+        log(f"forward overlapped {extra['forward_overlapped_ms']:.4f} ms "
+            f"({extra['forward_overlapped_phi16_ms']:.4f} ms with 16 ring pairs per phi workgroup), "
+            f"again as tuned {extra['forward_again_ms']:.4f} ms")
         # plain per-field launches: one plan per field, its two passes on the
         # caller's stream
         plans = [Plan(R, T, P, 1, parity=w.parity[f:f + 1], L=w.L[f:f + 1], rho=w.rho) for f in range(F)]

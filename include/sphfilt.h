@@ -206,7 +206,9 @@ int sphfilt_workload_stats(int n_r, int n_theta, int n_phi, int n_fields, const 
  *               theta_cols apart.  The default is the widest such tile.
  *               0 keeps the value.
  *   phi_lines   ring pairs per workgroup of the phi kernel: 4, 8, 16, 32 or
- *               64 (at most 256 lanes per workgroup).  0 keeps the value.
+ *               64 (at most 256 lanes per workgroup).  The default is 4 at
+ *               n_phi = 256, 8 at 64, 128, 160 and 192, and a full
+ *               256-lane workgroup otherwise.  0 keeps the value.
  * Returns SPHFILT_EINVAL for other values.  Not thread-safe against
  * concurrent apply calls on the same plan.
  */
@@ -292,10 +294,13 @@ int sphfilt_plan_get_theta_variant(sphfilt_plan plan, int *variant);
  * rings independent of them, and released by sphfilt_plan_destroy; no call
  * creates them, so a call can be captured in a HIP graph.  Enqueueing takes a
  * lock of the plan.
- *   mode  0: both passes on the caller's stream;
- *         1 (the default): overlap when those rings move at least 128 MiB
- *           (below that the fork and join cost more than they hide);
+ *   mode  0 (the default): both passes on the caller's stream;
+ *         1: overlap when those rings move at least 128 MiB (below that the
+ *           fork and join cost more than they hide);
  *         2: overlap whenever there is theta work and such a ring.
+ * With the default phi launch shape the overlapped passes measured slower
+ * than the two passes in a row (the second stream's small workgroups crowd
+ * the theta pass); sphfilt_plan_tune tries every mode.
  * set_overlap returns SPHFILT_EINVAL for other values; get_overlap needs a
  * non-NULL output.
  */

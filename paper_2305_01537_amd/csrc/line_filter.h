@@ -329,8 +329,10 @@ constexpr int line_stride()
 // Y[t + N2 r][n2] in v[r * N2 + n2].  Real and imaginary parts go through LDS
 // in two rounds to halve the LDS footprint.  With a padded second stage
 // (NV > N1: N2 does not divide N1) the rows t + N2 r >= N1 do not exist and
-// are set to zero.
-template <int N1, int N2, int NV>
+// are set to zero.  Only the line's own lanes touch its region L, so with
+// WAVE (the line's lanes in one wave) the wave-level ordering replaces the
+// workgroup barriers.
+template <int N1, int N2, bool WAVE, int NV>
 __device__ __forceinline__ void transpose_fwd(cplx (&v)[NV], int t, double *L)
 {
     constexpr int S = N2 + 1;
@@ -341,7 +343,7 @@ __device__ __forceinline__ void transpose_fwd(cplx (&v)[NV], int t, double *L)
             constexpr int k1 = decltype(kk)::value;
             L[k1 * S + t] = im ? v[k1].im : v[k1].re;
         });
-        __syncthreads();
+        line_sync<WAVE>();
         static_for<0, NV / N2>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
             const bool row = !PAD || t + N2 * r < N1;
@@ -351,12 +353,12 @@ __device__ __forceinline__ void transpose_fwd(cplx (&v)[NV], int t, double *L)
                 if constexpr (im) v[r * N2 + n2].im = x; else v[r * N2 + n2].re = x;
             });
         });
-        __syncthreads();
+        line_sync<WAVE>();
     });
 }
 
 // Inverse of transpose_fwd (padded rows are dropped).
-template <int N1, int N2, int NV>
+template <int N1, int N2, bool WAVE, int NV>
 __device__ __forceinline__ void transpose_bwd(cplx (&v)[NV], int t, double *L)
 {
     constexpr int S = N2 + 1;
@@ -373,13 +375,13 @@ __device__ __forceinline__ void transpose_bwd(cplx (&v)[NV], int t, double *L)
                 L[(t + N2 * r) * S + n2] = im ? v[r * N2 + n2].im : v[r * N2 + n2].re;
             });
         });
-        __syncthreads();
+        line_sync<WAVE>();
         static_for<0, N1>([&](auto kk) {
             constexpr int k1 = decltype(kk)::value;
             const double x = L[k1 * S + t];
             if constexpr (im) v[k1].im = x; else v[k1].re = x;
         });
-        __syncthreads();
+        line_sync<WAVE>();
     });
 }
 
@@ -417,9 +419,10 @@ __device__ __forceinline__ void twiddle_powers(cplx (&v)[NV], const Twiddle *__r
 // Filter one complex line of length N = N1 * N2 held by N2 lanes (lane t
 // holds x[N2 n1 + t] in v[n1]); on return v holds the filtered values at the
 // same positions.  Every lane of the workgroup calls this together.
-// etab: e^{-k}, k <= N/2, in LDS, written before the first barrier here.
-// WAVE (hybrid-capable variant): the line's lanes lie in one wave and
-// `mixed` is wave-uniform, so the two-kind mask synchronises the wave only.
+// etab: e^{-k}, k <= N/2, in LDS, written before the first barrier here
+// (with WAVE: before a barrier of the caller's).  WAVE: the line's lanes lie
+// in one wave, so the transposes and the two-kind mask synchronise the wave
+// only, with no workgroup barrier, and `mixed` is wave-uniform.
 template <int N1, int N2, bool HYB, bool WAVE = false, int NV>
 __device__ __forceinline__ void filter_line(cplx (&v)[NV], int t, int kind, int kind_b, bool mixed,
                                             double c, double *L, const Twiddle *__restrict__ tw,
@@ -434,7 +437,7 @@ __device__ __forceinline__ void filter_line(cplx (&v)[NV], int t, int kind, int 
     // forward: N1-point DFTs over n1, twiddle W_N^{t k1}
     dft_reg<N1, false>(v);
     twiddle_powers<N1, false, 0>(v, tw, t);
-    transpose_fwd<N1, N2>(v, t, L);
+    transpose_fwd<N1, N2, WAVE>(v, t, L);
     // N2-point DFTs over n2: v[r N2 + k2] = X[k1 + N1 k2], k1 = t + N2 r
     static_for<0, R>([&](auto rr) { dft_reg<N2, false, decltype(rr)::value * N2>(v); });
 
@@ -470,7 +473,7 @@ __device__ __forceinline__ void filter_line(cplx (&v)[NV], int t, int kind, int 
         const int k1 = t + N2 * r;
         twiddle_powers<N2, true, r * N2>(v, tw_inv, PAD && k1 >= N1 ? 0 : k1);
     });
-    transpose_bwd<N1, N2>(v, t, L);
+    transpose_bwd<N1, N2, WAVE>(v, t, L);
     dft_reg<N1, true>(v);
 }
 
@@ -798,6 +801,9 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
                       : cplx{0.0, 0.0};
     });
     if (any_active) {
+        // the line filter synchronises each line's wave only: the e^{-k}
+        // table staged above needs this one workgroup barrier
+        __syncthreads();
         double *L = lds + p * line_stride<N1, N2, HYB>();
         const size_t ring_b = (size_t)it.ring + (size_t)(n_theta - 1 - 2 * j);
         int ka = it.flags & kKindMask, kb = ka;
@@ -820,6 +826,9 @@ __device__ __forceinline__ void phi_block(const double *in, double *out,
             st_stream<SPHFILT_NT_STORE_PHI != 0>(out + b + N2 * n1 + t, ld_stream(in + b + N2 * n1 + t));
         });
     }
+    // a caller that runs another worker next (the batch kernels) must not
+    // overwrite the LDS before every wave is done with its lines
+    __syncthreads();
 }
 
 }  // namespace sphfilt
@@ -1060,6 +1069,9 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
                                  ring + (size_t)(N / 2 - 1 - 2 * j), hp, &ka, &kb, &mixed);
         }
         filter_line<N1, N2, HYB, true>(v, tp, ka, kb, mixed, c_p, L, tw, etab);
+        // the phi line filter synchronises each line's wave only; its LDS
+        // scratch overlaps the staging area and other lines' scratch
+        __syncthreads();
     };
 
     // the theta pass on the staged shells, ending with their contents updated
@@ -1110,6 +1122,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
     } else {
         if constexpr (phi_direct) {
             shell_phi_hbm<N, true>(in, out, base_p, v, tp, j, valid_p);
+            __syncthreads();                    // the e^{-k} table staged above
         } else {
             shell_phi_io<N, false>(v, sb_p, tp, j);
             __syncthreads();

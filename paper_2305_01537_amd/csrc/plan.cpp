@@ -411,7 +411,8 @@ int warm_plan(sphfilt_plan p, double *x, hipStream_t s)
 // Coordinate descent from the plan's current schedule over the theta tile
 // width, the ring pairs per phi workgroup, fused shells (where the grid has
 // them), the theta variant (where the circulant product applies) and the
-// overlap mode (where the plan has a side stream); each candidate is timed
+// overlap mode (where the plan has a side stream; then also every ring-pair
+// count with each overlapping mode); each candidate is timed
 // as a forward filter in place on zeroed scratch fields of the plan's size.
 int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
 {
@@ -471,12 +472,25 @@ int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
             c.theta_mfma = m;
             try_sched(c);
         }
-    if (p->side.state == 1)
+    if (p->side.state == 1) {
         for (int o : {0, 1, 2}) {
             PlanSched c = best;
             c.overlap = o;
             try_sched(c);
         }
+        // the phi launch shape and the overlap interact (small phi
+        // workgroups on the second stream crowd the theta pass): every shape
+        // with each overlapping mode
+        const PlanSched base = best;
+        for (int l : {4, 8, 16, 32, 64})
+            for (int o : {1, 2})
+                if (phi_shape_ok(p->n_phi, l)) {
+                    PlanSched c = base;
+                    c.phi_lines = l;
+                    c.overlap = o;
+                    try_sched(c);
+                }
+    }
     // confirm: the pick against the starting settings, three alternating
     // rounds each; keep the pick only if it is faster by more than 1 %
     if (!rc && !(best == start)) {
@@ -527,6 +541,21 @@ int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
     return SPHFILT_OK;
 }
 
+// A plan's default ring pairs per phi workgroup: the fastest measured for
+// the phi pass alone on dense MI355X grids (smaller workgroups hold fewer
+// waves at each barrier and drain more evenly): 4 at n_phi = 256 (265
+// against 270 us for 16), 8 at 64, 128, 160 and 192 (1-4 % faster than a
+// full 256-lane workgroup); a full workgroup elsewhere.  The batch kernels
+// keep full workgroups.
+int plan_phi_lines(int n_phi)
+{
+    switch (n_phi) {
+    case 256: return 4;
+    case 64: case 128: case 160: case 192: return 8;
+    default: return default_phi_lines(n_phi);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -563,10 +592,10 @@ int sphfilt_plan_create(sphfilt_plan *out, int n_r, int n_theta, int n_phi, int 
     p->n_fields = n_fields;
     p->theta_cols = default_theta_cols(2 * n_theta, n_phi);
     p->hybrid = hybrid_args(cut, n_fields);
-    p->phi_lines = default_phi_lines(n_phi);
+    p->phi_lines = plan_phi_lines(n_phi);
     p->fused = 1;
     p->theta_mfma = 0;
-    p->overlap = 1;
+    p->overlap = 0;
     p->params_hash = hash_params(n_r, n_theta, n_phi, n_fields, parity, cut);
     p->tuned_us = p->default_us = -1.0;
     try {

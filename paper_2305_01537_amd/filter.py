@@ -241,8 +241,8 @@ class Plan:
 
     def set_overlap(self, mode: int):
         """In place, run the rings that do not depend on the theta pass on a
-        second stream of the plan: 0 never, 1 when they move >= 128 MiB (the
-        default), 2 always; see sphfilt_plan_set_overlap."""
+        second stream of the plan: 0 never (the default), 1 when they move
+        >= 128 MiB, 2 always; see sphfilt_plan_set_overlap."""
         _lib.check("sphfilt_plan_set_overlap", self._lib.sphfilt_plan_set_overlap(self._h, int(mode)))
 
     def get_overlap(self) -> int:

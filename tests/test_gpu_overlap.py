@@ -64,7 +64,7 @@ def test_overlap_is_bitwise_the_two_pass_filter(torch_gpu, shape, kind, L):
     st = plan.stats()
     print(f"[gpu] overlap {shape}: theta shells {st['theta_shells_active']} of {F * R}", flush=True)
     assert 0 < st["theta_shells_active"] < F * R and plan.get_fused()[1] == 0
-    assert plan.get_overlap() == 1
+    assert plan.get_overlap() == 0
     for name, ref_fn in (("apply", oracle.forward), ("apply_adjoint", oracle.adjoint)):
         res = {}
         for ov in (2, 0):
