@@ -576,10 +576,11 @@ def main():
     value = points / (ms_fwd * 1e-3)
 
     # ---- per-kernel launches (same data, same stream) for the roofline -----
-    # each pass alone with the default launch shape (16 meridian pairs per
-    # theta sub-tile, 16 ring pairs per phi workgroup at these line lengths),
-    # whatever the tuner picked for the step, so that the roofline kernel's
-    # launch is the same in every run and in the profiler runs
+    # each pass alone with the default launch shape (16-line theta sub-tiles,
+    # 4 ring pairs per phi workgroup at these line lengths: the launches the
+    # default step makes), whatever the tuner picked for the step, so that the
+    # roofline kernel's launch is the same in every run and in the profiler
+    # runs
     kplan = Plan(R, T, P, F, parity=w.parity, L=w.L, rho=w.rho)
     ms_theta = time_loop(torch, lambda b: kplan.apply_theta(b, out=b), bufs, args.steps, 2, stream)
     ms_phi = time_loop(torch, lambda b: kplan.apply_phi(b, out=b), bufs, args.steps, 2, stream)
