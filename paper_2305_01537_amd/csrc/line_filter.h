@@ -772,7 +772,10 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
 // phi-pass worker.  LINES ring pairs per workgroup (LINES * N2 lanes, lane
 // (p, t) with t fastest): line p packs ring items[p].ring (real part) and its
 // mirror ring n_theta-1-j of the same shell (imaginary part), which shares
-// m_max.  Lines p >= n_valid are idle.  All lanes call this together.
+// m_max.  Lines p >= n_valid are idle.  A line's N2 lanes are consecutive
+// lanes of one wave, so the line filter synchronises per wave; the worker
+// itself takes three workgroup barriers (the any-active vote, the staged
+// e^{-k} table, the end).  All lanes call this together.
 // ---------------------------------------------------------------------------
 template <int N, int LINES, bool HYB>
 __device__ __forceinline__ void phi_block(const double *in, double *out,
