@@ -248,6 +248,45 @@ def test_empty_and_tiny_grids(torch_gpu):
     check_all(torch_gpu, x, np.array([1]), np.array([0.6]), kind=np.array([1], dtype=np.int32))
 
 
+@pytest.mark.parametrize("n_theta,n_phi", [(16, 32), (24, 32), (64, 128), (128, 256), (40, 80)])
+def test_sharp_below_mode_one_vanishes_for_odd_parity(torch_gpu, n_theta, n_phi):
+    """The degenerate cut-off: sharp masks below mode 1 in both directions keep theta
+    mode 0 and ring mode 0 only, so an even field becomes its shell mean and an odd
+    one vanishes exactly (the halves of every extended line cancel).  Plans (fused
+    shells and two passes) and a batch, forward and adjoint, must give the mean and
+    zero to round-off of the input's scale; a relative bar on a zero result would
+    compare round-off with round-off."""
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Batch, Plan
+    rng = np.random.default_rng(n_theta + n_phi)
+    x = rng.standard_normal((2, 3, n_theta, n_phi)) + 1.5
+    parity, kind, L = np.array([1, -1], dtype=np.int32), np.array([2, 2], dtype=np.int32), np.array([0.1, 0.1])
+    scale = np.abs(x).max()
+    mean = x[0].mean(axis=(1, 2))[:, None, None]
+    print(f"[gpu] vanishing odd field {x.shape}", flush=True)
+    plan = Plan(3, n_theta, n_phi, 2, parity=parity, L=L, kind=kind, floor_modes=0.5)
+    batch = Batch([dict(n_fields=2, n_r=3, n_theta=n_theta, n_phi=n_phi, parity=parity, L=L,
+                        kind=kind, floor_modes=0.5)])
+    for adjoint in (False, True):
+        ref = (oracle.adjoint if adjoint else oracle.forward)(x, parity=parity, L=L, kind=kind,
+                                                              floor_modes=0.5)
+        outs = []
+        for fused in (True, False):
+            plan.set_fused(fused)
+            outs.append(gpu_call(torch, plan, "adjoint" if adjoint else "forward", x, inplace=False))
+        xd = torch.from_numpy(x).cuda()
+        yd = batch.apply([xd], adjoint=adjoint)[0]
+        torch.cuda.synchronize()
+        outs.append(yd.cpu().numpy())
+        for y in outs:
+            assert np.abs(y - ref).max() <= 1e-14 * scale
+            assert np.abs(y[0] - mean).max() <= 1e-14 * scale
+            assert np.abs(y[1]).max() <= 1e-14 * scale
+    assert batch.status() == 0
+    batch.close()
+    plan.close()
+
+
 def test_grmhd_full_forward_adjoint(torch_gpu):
     w = synth.workload("grmhd")
     print(f"[gpu] grmhd full {w.shape}", flush=True)

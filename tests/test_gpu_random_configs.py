@@ -55,6 +55,23 @@ def draw(seed):
     return x, parity, kind, L, rho, floor, call
 
 
+# lanes per line in the kernels (the second factor of the line's split)
+LANES = {32: 4, 48: 4, 64: 8, 80: 8, 96: 8, 128: 8, 160: 16, 192: 16, 256: 16}
+
+
+def draw_shape(seed, n_theta, n_phi):
+    """A launch shape the plan accepts: theta_cols in {4..64}, at most n_phi/4
+    and one theta workgroup's lines, with 2 theta_cols dividing n_phi/2;
+    phi_lines in {4..64} with at most 256 lanes per workgroup.  Drawn from a
+    generator of its own, so the rest of the case does not depend on it."""
+    rng = np.random.default_rng(5000 + seed)
+    n = 2 * n_theta
+    cap = 256 // LANES[n]
+    cols = [c for c in (4, 8, 16, 32, 64) if c <= n_phi // 4 and c <= cap and (n_phi // 2) % (2 * c) == 0]
+    lines = [q for q in (4, 8, 16, 32, 64) if q * LANES[n_phi] <= 256]
+    return int(rng.choice(cols)), int(rng.choice(lines))
+
+
 def run(torch, plan, x, call):
     xd = torch.from_numpy(x).cuda()
     fn = plan.apply_adjoint if call["adjoint"] else plan.apply
@@ -63,11 +80,17 @@ def run(torch, plan, x, call):
     return y.cpu().numpy()
 
 
-def rel(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+def rel(a, b, x):
+    """Max-norm of a - b relative to the larger of b's max-norm and 1 % of the
+    input x's.  A filtered field can vanish exactly (an odd-parity field whose
+    kept modes are theta mode 0 and ring mode 0 only: the two halves of each
+    extended line cancel), and then only the round-off of either side is left
+    to compare; results that do not vanish stay above 0.4 % of the input's
+    max-norm over these draws, so for them the bar is the plain relative one."""
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-2 * np.abs(x).max(), 1e-300))
 
 
-@pytest.mark.parametrize("seed", range(48))
+@pytest.mark.parametrize("seed", range(240))
 def test_random_configuration(torch_gpu, seed):
     torch = torch_gpu
     from paper_2305_01537_amd.filter import Plan
@@ -75,15 +98,21 @@ def test_random_configuration(torch_gpu, seed):
     F, R, T, P = x.shape
     print(f"[gpu] case {seed}: {x.shape} kind {kind.tolist()} {call}", flush=True)
     plan = Plan(R, T, P, F, parity=parity, L=L, rho=rho, kind=kind, floor_modes=floor)
+    default_shape = plan.get_schedule()
+    shape = draw_shape(seed, T, P)
+    print(f"[gpu] case {seed}: launch shape {shape}", flush=True)
+    plan.set_schedule(*shape)
     plan.set_fused(call["fused"])
     plan.set_overlap(call["overlap"])
     got = run(torch, plan, x, call)
     ref_fn = oracle.adjoint if call["adjoint"] else oracle.forward
     ref = ref_fn(x, parity=parity, rho=rho, L=L, kind=kind, floor_modes=floor)
-    assert rel(got, ref) <= TOL, (seed, rel(got, ref))
-    # the plain schedule: both passes on the caller's stream, no fused shells
+    assert rel(got, ref, x) <= TOL, (seed, rel(got, ref, x))
+    # the plain schedule: both passes on the caller's stream, no fused shells,
+    # the default launch shape
+    plan.set_schedule(*default_shape)
     plan.set_fused(False)
     plan.set_overlap(0)
     plain = run(torch, plan, x, call)
-    assert rel(got, plain) <= 1e-14, (seed, rel(got, plain))
+    assert rel(got, plain, x) <= 1e-14, (seed, rel(got, plain, x))
     plan.close()

@@ -414,6 +414,28 @@ def test_p9_identity_when_cutoff_above_all_modes(oracle_mod):
 
 
 # --------------------------------------------------------------------------
+# P11: sharp cutoffs below mode 1 in both directions (floor 0.5, 2 rho L < 1)
+# keep theta mode 0 and ring mode 0 only.  Even parity: the extended line's
+# mean is that of both meridians, and the ring mean of those is the mean of
+# the whole shell, in either order.  Odd parity: the extended line's second
+# half is the negated partner meridian, so the forward filter leaves +mu and
+# -mu on the two meridians of a pair (ring mean zero) and the adjoint leaves
+# a ring-constant field whose extended lines have mean zero: both vanish.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("T,P", [(8, 16), (24, 32), (12, 48), (16, 16)])
+def test_p11_sharp_below_mode_one_is_the_shell_mean_or_zero(oracle_mod, T, P):
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal((2, 3, T, P)) + 1.5
+    kw = dict(parity=np.array([1, -1]), L=0.1, kind=SHARP, floor_modes=0.5)
+    mean = x[0].mean(axis=(1, 2))[:, None, None]
+    for fn in (oracle_mod.forward, oracle_mod.adjoint):
+        y = fn(x, **kw)
+        assert np.abs(y[0] - mean).max() <= 1e-14 * np.abs(x).max()
+        assert np.abs(y[1]).max() <= 1e-14 * np.abs(x).max()
+    assert np.abs(mean).max() > 0.5
+
+
+# --------------------------------------------------------------------------
 # P10: a library-FFT implementation of the same steps agrees.
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", [EXP, GAUSS, SHARP])
