@@ -242,9 +242,7 @@ int sphfilt_plan_get_fused(sphfilt_plan plan, int *enable, int *shells_fused);
  * overlap mode, by coordinate descent from the plan's current settings, each
  * candidate timed as forward filters in place, back to back (as a
  * time-stepping loop calls them), on scratch fields of the plan's size that
- * the call allocates and frees and fills with a constant positive value (the
- * filter's work does not depend on the values; the shock detector of hybrid
- * fields then takes its usual fast path).  The untuned settings are a
+ * the call allocates and frees.  The untuned settings are a
  * candidate, so the pick is never slower than them by the tuner's own
  * measurement.
  *   tune_cache_path  a JSON file shared with the batch tuner: if it holds
@@ -338,9 +336,8 @@ typedef struct {
  *   tune_cache_path  a JSON file: if it holds a schedule for this set of
  *                    patches on this GPU architecture, that schedule is used;
  *                    if not, the autotuner times the candidate schedules (see
- *                    sphfilt_batch_schedule) on scratch fields it allocates,
- *                    fills with a constant as a plan's tuner does, and frees,
- *                    and records the winner there (SPHFILT_EINVAL
+ *                    sphfilt_batch_schedule) on scratch fields it allocates
+ *                    and frees, and records the winner there (SPHFILT_EINVAL
  *                    if the file cannot be written).  NULL: the file named by
  *                    the environment variable SPHFILT_TUNE_CACHE if it is set
  *                    and not empty, else the untuned default schedule.

@@ -659,7 +659,7 @@ int tune(sphfilt_batch b, const char *cache_path)
     }
     hipStream_t s = nullptr;
     int rc = SPHFILT_OK;
-    if (hipMemset(scratch, kTuneFillByte, sizeof(double) * (size_t)total) != hipSuccess ||
+    if (hipMemset(scratch, 0, sizeof(double) * (size_t)total) != hipSuccess ||
         hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
         rc = SPHFILT_EDEVICE;
 

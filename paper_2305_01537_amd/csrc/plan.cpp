@@ -413,8 +413,7 @@ int warm_plan(sphfilt_plan p, double *x, hipStream_t s)
 // them), the theta variant (where the circulant product applies) and the
 // overlap mode (where the plan has a side stream; then also every ring-pair
 // count with each overlapping mode); each candidate is timed
-// as a forward filter in place on scratch fields of the plan's size holding a
-// constant positive value (kTuneFillByte).
+// as a forward filter in place on zeroed scratch fields of the plan's size.
 int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
 {
     const size_t n = (size_t)p->n_fields * p->n_r * p->n_theta * p->n_phi;
@@ -423,7 +422,7 @@ int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? SPHFILT_ENOMEM : SPHFILT_EDEVICE;
     hipStream_t s = nullptr;
     int rc = SPHFILT_OK;
-    if (hipMemset(x, kTuneFillByte, sizeof(double) * n) != hipSuccess ||
+    if (hipMemset(x, 0, sizeof(double) * n) != hipSuccess ||
         hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
         rc = SPHFILT_EDEVICE;
     const PlanSched start = plan_sched(p);

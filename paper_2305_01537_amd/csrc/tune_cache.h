@@ -29,14 +29,6 @@ bool tune_cache_get(const char *path, const std::string &sig, TuneFields *out);
 // false if the file cannot be written.
 bool tune_cache_put(const char *path, const std::string &sig, const TuneFields &fields);
 
-// The byte the tuners fill their scratch fields with: every double is then
-// 0x3f3f3f3f3f3f3f3f (about 4.8e-4), a constant positive field.  The filter's
-// arithmetic does not depend on the values, but the shock detector's does: on
-// zeros every cell is 0/0 and takes its exact-division fallback, a slow path
-// that real fields almost never take; on a constant field every cell takes
-// the fast sign test (and none fires).
-constexpr int kTuneFillByte = 0x3f;
-
 // Field helpers: numbers and strings.
 std::string tune_num(double v);
 std::string tune_str(const std::string &s);
