@@ -80,6 +80,27 @@ def test_noalloc_equals_batch_apply_two_calls(schedule):
             assert err <= 1e-12, err
 
 
+def test_noalloc_hybrid_and_mixed_radix_patches():
+    """The other kernel instances through the allocation-free call: hybrid fields
+    (the detector decides from the data) and lines of 48, 96 and 160 points,
+    two calls in a row, the second on a smaller batch."""
+    import torch
+    big = make_patches([(3, 5, 24, 48), (2, 4, 48, 96), (2, 3, 80, 160), (3, 4, 64, 128)], seed=73)
+    small = make_patches([(2, 3, 24, 48)], seed=74)
+    for patches in (big, small):
+        for p in patches:
+            p["kind"][0] = 3
+            p["x"][0] += 2.0
+            p["x"][0, 0, :, : p["n_phi"] // 3] = 0.0          # a jump for the detector
+    for patches, adjoint, inplace in ((big, False, True), (small, True, False)):
+        got, ref = run_pair(torch, patches, (1, -1), adjoint, inplace)
+        for p, g, r in zip(patches, got, ref):
+            assert np.array_equal(g, r), "noalloc differs from sphfilt_batch_apply"
+            want = oracle_out(p, adjoint)
+            err = np.abs(g - want).max() / np.abs(want).max()
+            assert err <= 1e-12, err
+
+
 def test_noalloc_rejects_sizes_beyond_the_array():
     """More patches or shells than the static array holds: SPHFILT_EUNSUPPORTED,
     decided on the host before any device call (the pointers passed are
