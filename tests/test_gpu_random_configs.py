@@ -8,7 +8,9 @@ scales over two decades, a radius table (uniform, stretched or None), a floor,
 the call (forward or adjoint, in place or out of place) and the schedule
 (fused shells and overlap on or off, theta tile and ring pairs per
 workgroup).  The result must match the oracle to 1e-12 relative max-norm, and
-the same call with the plain two-pass schedule to 1e-14.
+the same call with the plain two-pass schedule to 1e-14.  With field 0 made
+hybrid, recorded and replayed decisions give bitwise the same field and equal
+the oracle's decisions.
 """
 import numpy as np
 import pytest
@@ -115,4 +117,44 @@ def test_random_configuration(torch_gpu, seed):
     plan.set_overlap(0)
     plain = run(torch, plan, x, call)
     assert rel(got, plain, x) <= 1e-14, (seed, rel(got, plain, x))
+    plan.close()
+
+
+@pytest.mark.parametrize("seed", range(64))
+def test_random_hybrid_record_and_replay(torch_gpu, seed):
+    """The same draws with field 0 made hybrid (level 2 added, so its lines mix
+    smooth stretches and the jumps of the noise): recording the detector's
+    decisions and replaying them gives bitwise the same field, the field
+    matches the oracle, and every recorded decision of a hybrid field equals
+    the oracle's (theta decisions on the first pass's input, phi decisions on
+    the theta-filtered field, or the reverse for the adjoint)."""
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Plan
+    x, parity, kind, L, rho, floor, call = draw(seed)
+    kind = kind.copy()
+    kind[0] = 3
+    x = x.copy()
+    x[0] += 2.0
+    F, R, T, P = x.shape
+    print(f"[gpu] hybrid record/replay case {seed}: {x.shape} kind {kind.tolist()} {call}", flush=True)
+    plan = Plan(R, T, P, F, parity=parity, L=L, rho=rho, kind=kind, floor_modes=floor)
+    plan.set_fused(call["fused"])
+    plan.set_overlap(call["overlap"])
+    adj = call["adjoint"]
+    th, ph = plan.decision_buffers()
+    xd = torch.from_numpy(x).cuda()
+    rec = plan.apply_ex(xd, adjoint=adj, theta_dec=th, phi_dec=ph)
+    rep = plan.apply_ex(xd, adjoint=adj, theta_dec=th, phi_dec=ph, replay=True)
+    torch.cuda.synchronize()
+    a, b = rec.cpu().numpy(), rep.cpu().numpy()
+    assert np.array_equal(a, b)
+    kw = dict(parity=parity, rho=rho, L=L, kind=kind, floor_modes=floor)
+    ref = (oracle.adjoint if adj else oracle.forward)(x, **kw)
+    assert rel(a, ref, x) <= TOL
+    first = oracle.phi_pass(x, **kw) if adj else oracle.theta_pass(x, **kw)
+    th_ref = oracle.decisions(first if adj else x, parity=parity, kind=kind)[0]
+    ph_ref = oracle.decisions(x if adj else first, parity=parity, kind=kind)[1]
+    hyb = kind == 3
+    assert np.array_equal(th.cpu().numpy()[hyb], th_ref[hyb])
+    assert np.array_equal(ph.cpu().numpy()[hyb], ph_ref[hyb])
     plan.close()
