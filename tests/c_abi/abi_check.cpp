@@ -6,7 +6,11 @@
 //   - linearity with an exact scale: F(2 x) = 2 F(x) bit for bit (every step
 //     is a sum of products with the data, and scaling by 2 is exact);
 //   - in place equals out of place, bit for bit;
-//   - a batch of the same patch equals the plan, bit for bit;
+//   - a batch of the same patch equals the plan, bit for bit, and the
+//     allocation-free batch call equals the batch call;
+//   - hybrid fields: replaying recorded decisions gives the recorded field bit
+//     for bit, and the adjoint that replays a forward call's decisions is its
+//     transpose (<F_D x, y> = <x, F_D^T y> to 1e-13);
 //   - argument errors come back as status codes before any device work.
 // Prints one line per check and "abi_check: ok"; exits non-zero on failure.
 #include "../../include/sphfilt.h"
@@ -150,6 +154,61 @@ int main()
     expect(moved, "the filter changes the field");
     expect(std::memcmp(xin.data(), x.data(), bytes) == 0, "out of place leaves the input untouched");
     expect(std::memcmp(fb.data(), fx.data(), bytes) == 0, "batch equals plan bit for bit");
+
+    // the allocation-free call on the same batch, in place on another copy of x
+    ok = hip_ok(hipMemcpy(db, x.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy");
+    expect(sphfilt_batch_apply_noalloc(batch, ins, outs, 0, s) == SPHFILT_OK, "sphfilt_batch_apply_noalloc");
+    std::vector<double> fn(n);
+    ok = ok && hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize") &&
+         hip_ok(hipMemcpy(fn.data(), db, bytes, hipMemcpyDeviceToHost), "hipMemcpy");
+    expect(ok && std::memcmp(fn.data(), fb.data(), bytes) == 0, "allocation-free call equals the batch call");
+
+    // hybrid fields 0 and 2: field 0 is a level of 2 with a jump to zero on
+    // every shell's first rows, field 2 keeps the signed noise
+    const int kind_h[n_fields] = {SPHFILT_HYBRID, SPHFILT_EXP, SPHFILT_HYBRID};
+    const sphfilt_cutoff cut_h = {nullptr, L, kind_h, 2.0, 0.0, 0.0};
+    sphfilt_plan hp = nullptr;
+    expect(sphfilt_plan_create(&hp, n_r, n_theta, n_phi, n_fields, parity, &cut_h) == SPHFILT_OK,
+           "hybrid sphfilt_plan_create");
+    std::vector<double> xh = x;
+    const size_t shell = (size_t)n_theta * n_phi;
+    for (int i = 0; i < n_r; ++i)
+        for (size_t k = 0; k < shell; ++k) xh[i * shell + k] = k < shell / 8 ? 0.0 : 2.0 + 0.1 * x[i * shell + k];
+    const size_t n_th = (size_t)n_fields * n_r * (n_phi / 2), n_ph = (size_t)n_fields * n_r * n_theta;
+    unsigned char *dth = nullptr, *dph = nullptr;
+    double *dxh = nullptr, *drec = nullptr, *drep = nullptr, *dadj = nullptr;
+    ok = hip_ok(hipMalloc((void **)&dth, n_th), "hipMalloc") && hip_ok(hipMalloc((void **)&dph, n_ph), "hipMalloc") &&
+         hip_ok(hipMalloc((void **)&dxh, bytes), "hipMalloc") && hip_ok(hipMalloc((void **)&drec, bytes), "hipMalloc") &&
+         hip_ok(hipMalloc((void **)&drep, bytes), "hipMalloc") && hip_ok(hipMalloc((void **)&dadj, bytes), "hipMalloc") &&
+         hip_ok(hipMemset(dth, 0, n_th), "hipMemset") && hip_ok(hipMemset(dph, 0, n_ph), "hipMemset") &&
+         hip_ok(hipMemcpy(dxh, xh.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy");
+    if (!ok) return 1;
+    expect(sphfilt_apply_ex(hp, dxh, drec, 0, dth, dph, 0, s) == SPHFILT_OK, "hybrid forward, recording");
+    expect(sphfilt_apply_ex(hp, dxh, drep, 0, dth, dph, 1, s) == SPHFILT_OK, "hybrid forward, replaying");
+    expect(sphfilt_apply_ex(hp, dy, dadj, 1, dth, dph, 1, s) == SPHFILT_OK, "hybrid adjoint, replaying");
+    std::vector<double> rec(n), rep(n), adj(n);
+    std::vector<unsigned char> th(n_th), ph(n_ph);
+    ok = hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize") &&
+         hip_ok(hipMemcpy(rec.data(), drec, bytes, hipMemcpyDeviceToHost), "hipMemcpy") &&
+         hip_ok(hipMemcpy(rep.data(), drep, bytes, hipMemcpyDeviceToHost), "hipMemcpy") &&
+         hip_ok(hipMemcpy(adj.data(), dadj, bytes, hipMemcpyDeviceToHost), "hipMemcpy") &&
+         hip_ok(hipMemcpy(th.data(), dth, n_th, hipMemcpyDeviceToHost), "hipMemcpy") &&
+         hip_ok(hipMemcpy(ph.data(), dph, n_ph, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (!ok) return 1;
+    size_t fired = 0;
+    for (unsigned char c : th) fired += c;
+    for (unsigned char c : ph) fired += c;
+    std::printf("hybrid: %zu of %zu hybrid lines took the Gaussian\n", fired, (n_th + n_ph) * 2 / 3);
+    expect(fired > 0 && fired < (n_th + n_ph) * 2 / 3, "the detector fires on some hybrid lines, not all");
+    expect(std::memcmp(rec.data(), rep.data(), bytes) == 0, "replayed decisions give the recorded field");
+    const double ah = dot(rec, y), bh = dot(xh, adj);
+    const double relh = std::fabs(ah - bh) / std::fmax(std::fabs(ah), std::fabs(bh));
+    std::printf("hybrid dot test: relative difference %.3g\n", relh);
+    expect(relh <= 1e-13, "the adjoint with a forward call's decisions is its transpose");
+    sphfilt_plan_destroy(hp);
+    for (double *p : {dxh, drec, drep, dadj}) (void)hipFree(p);
+    (void)hipFree(dth);
+    (void)hipFree(dph);
 
     sphfilt_batch_destroy(batch);
     sphfilt_plan_destroy(plan);

@@ -1,8 +1,10 @@
 """The C-ABI from a program that links libsphfilt.so and uses no Python or
 PyTorch (tests/c_abi/abi_check.cpp, built by __graft_entry__.build()): the
 dot-product identity <F x, y> = <x, F^T y> to 1e-13, F(2x) = 2 F(x) bit for
-bit, in place equal to out of place, a batch equal to the plan, and status
-codes for bad arguments."""
+bit, in place equal to out of place, a batch equal to the plan and the
+allocation-free call equal to the batch call, hybrid decisions replayed bit
+for bit and the replayed adjoint the transpose, and status codes for bad
+arguments."""
 import os
 import subprocess
 
