@@ -204,7 +204,12 @@ int sphfilt_workload_stats(int n_r, int n_theta, int n_phi, int n_fields, const 
  *               pairs of each of its 256/lanes/theta_cols shells; each line
  *               packs two adjacent ones, or, where 2*n_theta = 256, two
  *               theta_cols apart.  The default is the widest such tile.
- *               0 keeps the value.
+ *               0 keeps the value.  For fields that are not hybrid the
+ *               plan's theta kernel runs workgroups of 128 lanes where that
+ *               measured faster (2*n_theta = 32, 48, 64, 96, 160, 192), and
+ *               there takes the smaller of theta_cols and the lines of 128
+ *               lanes (the result does not depend on the width at these
+ *               lengths).
  *   phi_lines   ring pairs per workgroup of the phi kernel: 4, 8, 16, 32 or
  *               64 (at most 256 lanes per workgroup).  The default is 4 at
  *               n_phi = 256, 8 at 64, 128, 160 and 192, and a full

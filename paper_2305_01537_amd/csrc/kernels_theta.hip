@@ -29,26 +29,48 @@ __global__ __launch_bounds__(C * Split<N>::N2) __attribute__((amdgpu_waves_per_e
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
+// Lanes per workgroup of the plan's plain theta kernel.  128 where that
+// measured faster on dense grids (theta pass: N = 48, 64 and 96 5-7 %, 160 and
+// 192 4 %, 32 1.5 %: half the waves wait at each barrier and the launch drains
+// in finer steps), 256 at 80, 128 and 256 (128 lanes: 1.5 %, 10 % and 45 %
+// slower).  Where pairs are adjacent (every N but 256) a line's result does
+// not depend on the tile width, so both shapes give the same bits.  The
+// hybrid-capable instance keeps 256 lanes.
+template <int N>
+constexpr int theta_plan_lanes()
+{
+    return N == 80 || N == 128 || N == 256 ? 256 : 128;
+}
+
+// One launch of theta_kernel<N, C, HYB> over the items; the tile width is
+// `cols`, or the workgroup's C lines where that is smaller.
+template <int N, int C, bool HYB>
+static hipError_t theta_launch(int cols, const double *in, double *out, const ThetaItem *items,
+                               int n_items, int n_theta, int n_phi, const Twiddle *tw,
+                               const double *eneg, const HybridArgs &h, hipStream_t s)
+{
+    const int cw = cols < C ? cols : C;
+    const int cp_log2 = ilog2_int(cw);
+    const int per_group = C / cw;
+    const int tiles = (n_phi / 2) / (2 * cw);
+    const int groups = (n_items + per_group - 1) / per_group;
+    theta_kernel<N, C, HYB><<<dim3((unsigned)(groups * tiles)), dim3(C * Split<N>::N2), 0, s>>>(
+        in, out, items, n_items, cp_log2, tiles, n_theta, n_phi, tw, eneg, h);
+    return hipGetLastError();
+}
+
 template <int N>
 static hipError_t theta_go(int cols, const double *in, double *out, const ThetaItem *items,
                            int n_items, int n_theta, int n_phi, const Twiddle *tw,
                            const double *eneg, const HybridArgs &h, hipStream_t s)
 {
-    constexpr int C = lines_per_256<N>();
-    const int cp_log2 = ilog2_int(cols);
-    const int per_group = C / cols;
-    const int tiles = (n_phi / 2) / (2 * cols);
-    const int groups = (n_items + per_group - 1) / per_group;
-    const dim3 grid((unsigned)(groups * tiles)), block(256);
     // the hybrid-capable variant only when the plan has hybrid fields: its
     // detector and two-kind mask cost registers the plain filter does not need
     if (h.present)
-        theta_kernel<N, C, true><<<grid, block, 0, s>>>(in, out, items, n_items, cp_log2, tiles,
-                                                        n_theta, n_phi, tw, eneg, h);
-    else
-        theta_kernel<N, C, false><<<grid, block, 0, s>>>(in, out, items, n_items, cp_log2, tiles,
-                                                         n_theta, n_phi, tw, eneg, h);
-    return hipGetLastError();
+        return theta_launch<N, lines_per_256<N>(), true>(cols, in, out, items, n_items, n_theta,
+                                                         n_phi, tw, eneg, h, s);
+    return theta_launch<N, theta_plan_lanes<N>() / Split<N>::N2, false>(
+        cols, in, out, items, n_items, n_theta, n_phi, tw, eneg, h, s);
 }
 
 hipError_t launch_theta(int n_line, int cols, const double *in, double *out,

@@ -695,7 +695,7 @@ __device__ __forceinline__ void theta_block(const double *in, double *out,
                                             double *etab, int *flags, const HybridArgs &h, int lane)
 {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-    static_assert(C * N2 == 256, "theta workgroups have 256 lanes");
+    static_assert(C * N2 == 256 || C * N2 == 128, "theta workgroups have 256 or 128 lanes");
     const int p = lane % C, t = lane / C;
     const int u = p >> cp_log2, pp = p & ((1 << cp_log2) - 1);
     const bool valid = u < n_valid;

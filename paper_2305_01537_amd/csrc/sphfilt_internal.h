@@ -88,7 +88,9 @@ int shells_per_group(int n_phi);
 
 // Launch shapes (kernels.hip).  A theta workgroup has 256 lanes holding
 // theta_lines_per_group(N) complex lines, split in sub-tiles of `cols` lines,
-// one shell per sub-tile; a phi workgroup holds `lines` ring pairs.
+// one shell per sub-tile (the plan's plain theta kernel runs 128-lane
+// workgroups at some N, see kernels_theta.hip); a phi workgroup holds `lines`
+// ring pairs.
 int lanes_per_line(int n_line);
 int ilog2_int(int v);
 int theta_lines_per_group(int n_line);
