@@ -12,19 +12,19 @@ namespace sphfilt {
 
 // Fused shells and, in the same grid, ring pairs of the other shells: blocks
 // [0, shell_groups) run shell_block on `shells`, the rest run phi_block
-// (256/N2 ring pairs each) on `rings`.  The two sets touch different shells,
+// (W/N2 ring pairs each) on `rings`; W lanes per workgroup.  The two sets touch different shells,
 // so one launch lets the ring-pair workgroups stream while the shell
 // workgroups load, filter and store their shells.  MFMA: the shells' theta
 // pass as the circulant product (theta_gemm.h).
-template <int N, bool ADJ, bool HYB, bool MFMA>
-__global__ __launch_bounds__(256) void shell_phi_kernel(
+template <int N, bool ADJ, bool HYB, bool MFMA, int W>
+__global__ __launch_bounds__(W) void shell_phi_kernel(
     const double *in, double *out, const ThetaItem *__restrict__ shells,
     const double *__restrict__ ring_c, int n_shells, int shell_groups,
     const PhiItem *__restrict__ rings, int n_rings, const Twiddle *__restrict__ tw,
     const double *__restrict__ eneg, HybridArgs ht, HybridArgs hp)
 {
-    using S = ShellShape<N>;
-    constexpr int LINES = 256 / Split<N>::N2;
+    using S = ShellShape<N, W>;
+    constexpr int LINES = W / Split<N>::N2;
     static_assert(S::lds >= LINES * line_stride<Split<N>::N1, Split<N>::N2, HYB>(), "ring-pair scratch");
     __shared__ double lds[S::lds];
     __shared__ double etab[N / 2 + 1];
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void shell_phi_kernel(
     __shared__ double gaux[MFMA ? shell_gemm_aux<N>() : 1];
     if ((int)blockIdx.x < shell_groups) {
         const int first = blockIdx.x * S::shells;
-        shell_block<N, ADJ, HYB, MFMA>(in, out, shells + first, ring_c + (size_t)first * S::lines,
+        shell_block<N, ADJ, HYB, MFMA, W>(in, out, shells + first, ring_c + (size_t)first * S::lines,
                                        min(S::shells, n_shells - first), tw, eneg, lds, etab,
                                        flags, ht, hp, threadIdx.x, gaux);
     } else {
@@ -168,6 +168,27 @@ int shells_per_group(int n_phi)
 }
 
 
+// Lanes per workgroup of the fused launch: 128 for plain kinds at N = 32 and
+// 64 (dense fused filter 2-7 % faster: fewer waves per barrier, and the
+// halved staging LDS lets twice as many workgroups share a CU), 256 for
+// N = 128 (one shell takes 256 lanes), for hybrid fields (their instance
+// needs more registers at 128 lanes) and for the circulant variant.
+template <int N, bool ADJ, bool HYB, bool MFMA>
+static hipError_t shell_phi_launch(const double *in, double *out, const ThetaItem *shells,
+                                   const double *ring_c, int n_shells, const PhiItem *rings,
+                                   int n_rings, const Twiddle *tw, const double *eneg,
+                                   const HybridArgs &ht, const HybridArgs &hp, hipStream_t s)
+{
+    constexpr int W = N <= 64 && !MFMA && !HYB ? 128 : 256;
+    constexpr int LINES = W / Split<N>::N2;
+    const int groups = (n_shells + ShellShape<N, W>::shells - 1) / ShellShape<N, W>::shells;
+    const dim3 grid((unsigned)(groups + (n_rings + LINES - 1) / LINES)), block(W);
+    shell_phi_kernel<N, ADJ, HYB, MFMA, W><<<grid, block, 0, s>>>(in, out, shells, ring_c, n_shells,
+                                                                  groups, rings, n_rings, tw, eneg,
+                                                                  ht, hp);
+    return hipGetLastError();
+}
+
 template <int N, bool MFMA>
 static hipError_t shell_phi_go(bool adjoint, const double *in, double *out,
                                const ThetaItem *shells, const double *ring_c, int n_shells,
@@ -175,20 +196,16 @@ static hipError_t shell_phi_go(bool adjoint, const double *in, double *out,
                                const double *eneg, const HybridArgs &ht, const HybridArgs &hp,
                                hipStream_t s)
 {
-    constexpr int LINES = 256 / Split<N>::N2;
-    const int groups = (n_shells + ShellShape<N>::shells - 1) / ShellShape<N>::shells;
-    const dim3 grid((unsigned)(groups + (n_rings + LINES - 1) / LINES)), block(256);
     const bool hyb = ht.present != 0;
 #define SPHFILT_SHELL_PHI(A, H)                                                                    \
-    shell_phi_kernel<N, A, H, MFMA && !H><<<grid, block, 0, s>>>(in, out, shells, ring_c, n_shells, \
-                                                                 groups, rings, n_rings, tw, eneg, ht, hp)
+    return shell_phi_launch<N, A, H, MFMA && !H>(in, out, shells, ring_c, n_shells, rings, n_rings, \
+                                                 tw, eneg, ht, hp, s)
     if (adjoint) {
         if (hyb) SPHFILT_SHELL_PHI(true, true); else SPHFILT_SHELL_PHI(true, false);
     } else {
         if (hyb) SPHFILT_SHELL_PHI(false, true); else SPHFILT_SHELL_PHI(false, false);
     }
 #undef SPHFILT_SHELL_PHI
-    return hipGetLastError();
 }
 
 bool theta_gemm_ok(int n_theta, int n_phi)

@@ -843,7 +843,7 @@ namespace sphfilt {
 // For n_phi = 2 n_theta = N a theta line and a phi ring have the same length
 // N, and a shell has as many complex theta lines (meridian pairs k and
 // k + N/4) as complex phi lines (ring pairs j and n_theta-1-j): N/4.  A
-// 256-lane workgroup takes `shells` whole shells: it loads their theta lines
+// workgroup of W lanes (256 or 128) takes `shells` whole shells: it loads their theta lines
 // from HBM, filters them, writes the result into a padded LDS copy of the
 // shells, reads it back in the phi layout, filters the rings and stores them
 // to HBM (the adjoint order runs the phi pass first).  Lines are filtered as
@@ -852,25 +852,25 @@ namespace sphfilt {
 // these N), so the result is that of the two passes up to rounding.  The line
 // filter's LDS scratch reuses the staging memory.
 // ---------------------------------------------------------------------------
-template <int N> struct ShellShape {
+template <int N, int W = 256> struct ShellShape {
     static constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
     static constexpr int lines = N / 4;                  // complex lines per shell and pass
     static constexpr int lanes = lines * N2;             // lanes per shell
-    static constexpr int shells = 256 / lanes;           // shells per workgroup
+    static constexpr int shells = W / lanes;             // shells per workgroup
     static constexpr int row = N + (N2 == 4 ? 4 : 8);    // padded row stride, doubles
     static constexpr int stride = (N / 2) * row + 16;    // doubles per staged shell
     static constexpr int lds = shells * stride;
     static_assert(lanes % N == 0, "a shell's lanes cover whole rows");
-    static_assert(lds >= (256 / N2) * line_stride<N1, N2, true>(), "scratch fits in the staging area");
+    static_assert(shells >= 1 && lds >= (W / N2) * line_stride<N1, N2, true>(), "scratch fits in the staging area");
 };
 
 // Staging: lane l of a shell's lanes moves elements e = k * lanes + l,
 // k < 2 N1, of the shell (row e / N, column e % N).
-template <int N, bool LOAD>
+template <int N, bool LOAD, int W = 256>
 __device__ __forceinline__ void shell_stage(const double *in, double *out, double *sb, cplx (&v)[Split<N>::N1],
                                             size_t base, bool valid, int l)
 {
-    using S = ShellShape<N>;
+    using S = ShellShape<N, W>;
     constexpr int R = S::lanes / N;                      // rows per k step
     const int r0 = l / N, col = l % N;
     static_for<0, 2 * S::N1>([&](auto kk) {
@@ -889,10 +889,10 @@ __device__ __forceinline__ void shell_stage(const double *in, double *out, doubl
 
 // theta layout: lane (p, t), p = lane % C fastest; line p packs meridian
 // pairs kr = p % lines and ki = kr + lines of staged shell p / lines.
-template <int N, bool WRITE>
+template <int N, bool WRITE, int W = 256>
 __device__ __forceinline__ void shell_theta_io(cplx (&v)[Split<N>::N1], double *sb, int t, int kr, double s)
 {
-    using S = ShellShape<N>;
+    using S = ShellShape<N, W>;
     constexpr int N1 = S::N1, N2 = S::N2, half = N / 2;
     const int ki = kr + S::lines;
     static_for<0, N1>([&](auto nn) {
@@ -913,12 +913,12 @@ __device__ __forceinline__ void shell_theta_io(cplx (&v)[Split<N>::N1], double *
 // doubles): the same positions as shell_theta_io, with no staging copy.  A
 // load or store instruction covers the lines' consecutive meridians of one
 // or two rows.  Invalid shells load zeros and store nothing.
-template <int N, bool LOAD>
+template <int N, bool LOAD, int W = 256>
 __device__ __forceinline__ void shell_theta_hbm(const double *in, double *out, size_t base,
                                                 cplx (&v)[Split<N>::N1], int t, int kr, double s,
                                                 bool valid)
 {
-    using S = ShellShape<N>;
+    using S = ShellShape<N, W>;
     constexpr int N1 = S::N1, N2 = S::N2, half = N / 2;
     constexpr bool cached = theta_loads_cached<N>();
     const int ki = kr + S::lines;
@@ -949,10 +949,10 @@ __device__ __forceinline__ void shell_theta_hbm(const double *in, double *out, s
 
 // phi layout: lane (p, t), t = lane % N2 fastest; line p packs rings j and
 // n_theta-1-j, j = p % lines, of staged shell p / lines.
-template <int N, bool WRITE>
+template <int N, bool WRITE, int W = 256>
 __device__ __forceinline__ void shell_phi_io(cplx (&v)[Split<N>::N1], double *sb, int t, int j)
 {
-    using S = ShellShape<N>;
+    using S = ShellShape<N, W>;
     constexpr int N1 = S::N1, N2 = S::N2;
     double *ra = sb + j * S::row + t;
     double *rb = sb + (N / 2 - 1 - j) * S::row + t;
@@ -996,7 +996,7 @@ constexpr int shell_gemm_aux()
     return ShellShape<N>::shells * (N / 2 + 1) + N + ShellShape<N>::shells * N;
 }
 
-template <int N, bool ADJ, bool HYB, bool MFMA = false>
+template <int N, bool ADJ, bool HYB, bool MFMA = false, int W = 256>
 __device__ __forceinline__ void shell_block(const double *in, double *out,
                                             const ThetaItem *__restrict__ items,
                                             const double *__restrict__ ring_c, int n_valid,
@@ -1006,8 +1006,9 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
                                             const HybridArgs &hp, int lane, double *gaux = nullptr)
 {
     static_assert(!MFMA || (!HYB && (N == 32 || N == 64)), "circulant theta: plain kinds, N = 32, 64");
-    using S = ShellShape<N>;
-    constexpr int N1 = S::N1, N2 = S::N2, C = 256 / N2;
+    static_assert(!MFMA || W == 256, "circulant variant: 256-lane workgroups");
+    using S = ShellShape<N, W>;
+    constexpr int N1 = S::N1, N2 = S::N2, C = W / N2;
     constexpr size_t shell_pts = (size_t)N * N / 2;
     stage_exp_table<N>(etab, eneg, lane);
 
@@ -1039,7 +1040,7 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
     double *sb_t = lds + ut * S::stride;
 
     if constexpr (stage_in) {
-        shell_stage<N, true>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
+        shell_stage<N, true, W>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
         __syncthreads();
     }
     // phi layout
@@ -1100,44 +1101,44 @@ __device__ __forceinline__ void shell_block(const double *in, double *out,
             });
         } else if constexpr (!ADJ) {
             // forward: the lines come from HBM, the result goes to the staging area
-            shell_theta_hbm<N, true>(in, out, base_t, v, tt, kr, sgn, valid_t);
+            shell_theta_hbm<N, true, W>(in, out, base_t, v, tt, kr, sgn, valid_t);
             theta_filter();
-            shell_theta_io<N, true>(v, sb_t, tt, kr, sgn);
+            shell_theta_io<N, true, W>(v, sb_t, tt, kr, sgn);
         } else {
             // adjoint: the lines come from the staging area, the result goes to HBM
-            shell_theta_io<N, false>(v, sb_t, tt, kr, sgn);
+            shell_theta_io<N, false, W>(v, sb_t, tt, kr, sgn);
             __syncthreads();
             theta_filter();
-            shell_theta_hbm<N, false>(in, out, base_t, v, tt, kr, sgn, valid_t);
+            shell_theta_hbm<N, false, W>(in, out, base_t, v, tt, kr, sgn, valid_t);
         }
     };
 
     if constexpr (!ADJ) {
         theta_pass();
         __syncthreads();
-        shell_phi_io<N, false>(v, sb_p, tp, j);
+        shell_phi_io<N, false, W>(v, sb_p, tp, j);
         __syncthreads();
         phi_filter();
         if constexpr (phi_direct)
             shell_phi_hbm<N, false>(in, out, base_p, v, tp, j, valid_p);
         else
-            shell_phi_io<N, true>(v, sb_p, tp, j);
+            shell_phi_io<N, true, W>(v, sb_p, tp, j);
     } else {
         if constexpr (phi_direct) {
             shell_phi_hbm<N, true>(in, out, base_p, v, tp, j, valid_p);
             __syncthreads();                    // the e^{-k} table staged above
         } else {
-            shell_phi_io<N, false>(v, sb_p, tp, j);
+            shell_phi_io<N, false, W>(v, sb_p, tp, j);
             __syncthreads();
         }
         phi_filter();
-        shell_phi_io<N, true>(v, sb_p, tp, j);
+        shell_phi_io<N, true, W>(v, sb_p, tp, j);
         __syncthreads();
         theta_pass();
     }
     if constexpr (stage_out) {
         __syncthreads();
-        shell_stage<N, false>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
+        shell_stage<N, false, W>(in, out, lds + us * S::stride, v, base_s, valid_s, lane % S::lanes);
     }
 }
 
