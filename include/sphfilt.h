@@ -212,7 +212,7 @@ int sphfilt_workload_stats(int n_r, int n_theta, int n_phi, int n_fields, const 
  *               lengths).
  *   phi_lines   ring pairs per workgroup of the phi kernel: 4, 8, 16, 32 or
  *               64 (at most 256 lanes per workgroup).  The default is 4 at
- *               n_phi = 256, 8 at 64, 128, 160 and 192, and a full
+ *               n_phi = 256, 8 at 64, 80, 96, 128, 160 and 192, and a full
  *               256-lane workgroup otherwise.  0 keeps the value.
  * Returns SPHFILT_EINVAL for other values.  Not thread-safe against
  * concurrent apply calls on the same plan.

@@ -544,14 +544,14 @@ int tune_plan(sphfilt_plan p, const std::string &arch, const char *cache_path)
 // A plan's default ring pairs per phi workgroup: the fastest measured for
 // the phi pass alone on dense MI355X grids (smaller workgroups hold fewer
 // waves at each barrier and drain more evenly): 4 at n_phi = 256 (265
-// against 270 us for 16), 8 at 64, 128, 160 and 192 (1-4 % faster than a
-// full 256-lane workgroup); a full workgroup elsewhere.  The batch kernels
-// keep full workgroups.
+// against 270 us for 16), 8 at 64, 80, 96, 128, 160 and 192 (1-4 % faster
+// than a full 256-lane workgroup); a full workgroup at 32 and 48, where that
+// is fastest.  The batch kernels keep full workgroups.
 int plan_phi_lines(int n_phi)
 {
     switch (n_phi) {
     case 256: return 4;
-    case 64: case 128: case 160: case 192: return 8;
+    case 64: case 80: case 96: case 128: case 160: case 192: return 8;
     default: return default_phi_lines(n_phi);
     }
 }
