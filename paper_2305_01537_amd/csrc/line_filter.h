@@ -42,10 +42,12 @@ __device__ __forceinline__ double ld_stream(const double *p)
 }
 
 // Loads whose instruction reads only a piece of each 128-byte line it
-// touches go through the cache instead: rings of N <= 64 points (4 or 8 lanes
-// per ring: 32- or 64-byte pieces) and theta rows at N = 32 (sub-tiles of 8
-// meridians).  Streamed, the other pieces of a line were fetched again (1.32x
-// the algorithmic bytes for rings of 32, 1.09x for rings of 64).
+// touches go through the cache instead: rings of N <= 128 points (4 or 8
+// lanes per ring: 32- or 64-byte pieces) and theta rows at N = 32 (sub-tiles
+// of 8 meridians).  Streamed, the other pieces of a line were fetched again
+// (1.32x the algorithmic bytes for rings of 32, 1.09x for rings of 64, 1.04x
+// for rings of 128; cached, the phi pass at 128 ran 1.3 % faster and the
+// fused grmhd call 3 %).
 template <bool CACHED>
 __device__ __forceinline__ double ld_piece(const double *p)
 {
@@ -55,7 +57,7 @@ __device__ __forceinline__ double ld_piece(const double *p)
         return ld_stream(p);
 }
 template <int N>
-constexpr bool ring_loads_cached() { return N <= 64; }
+constexpr bool ring_loads_cached() { return N <= 128; }
 // Ring stores of 32-byte pieces (4 lanes per ring: N = 32, 48) go through the
 // cache too, so that the pieces of a line are written back together (phi pass
 // at N = 32: 1.125x the algorithmic writes streamed, 1.8 % faster cached; at
