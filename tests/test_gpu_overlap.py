@@ -213,3 +213,53 @@ def test_one_plan_on_two_streams(torch_gpu, shape, overlap):
     for d, r in zip(bufs, ref):
         assert np.array_equal(d.cpu().numpy(), r)
     plan.close()
+
+
+def test_one_plan_from_two_host_threads(torch_gpu):
+    """Two host threads call one plan at once (the binding releases the
+    interpreter lock during the library call), each on its own stream and
+    fields, forward and adjoint in place: every result equals the same calls
+    made one after another."""
+    import threading
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Plan
+    shape = (2, 10, 128, 256)
+    xs = [fields(shape, s)[0] for s in (181, 182)]
+    _, parity = fields(shape, 181)
+    plan = Plan(10, 128, 256, 2, parity=parity, L=np.full(2, 9.0))
+    plan.set_overlap(2)
+
+    def calls(d):
+        for _ in range(10):
+            plan.apply(d, out=d)
+            plan.apply_adjoint(d, out=d)
+
+    ref = []
+    for x in xs:
+        d = torch.from_numpy(x).cuda()
+        calls(d)
+        torch.cuda.synchronize()
+        ref.append(d.cpu().numpy())
+    bufs = [torch.from_numpy(x).cuda() for x in xs]
+    torch.cuda.synchronize()
+    errors = []
+
+    def worker(d):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                calls(d)
+            s.synchronize()
+        except Exception as e:          # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(d,)) for d in bufs]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for d, r in zip(bufs, ref):
+        assert np.array_equal(d.cpu().numpy(), r)
+    plan.close()
