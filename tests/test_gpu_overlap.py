@@ -263,3 +263,46 @@ def test_one_plan_from_two_host_threads(torch_gpu):
     for d, r in zip(bufs, ref):
         assert np.array_equal(d.cpu().numpy(), r)
     plan.close()
+
+
+def test_plans_in_a_captured_graph(torch_gpu):
+    """Forward and adjoint calls of a fused-shell plan and of a two-pass plan
+    captured in one graph: every replay (with eager work and synchronisation
+    between replays) equals the same calls made eagerly."""
+    torch = torch_gpu
+    from paper_2305_01537_amd.filter import Plan
+    xa, pa = fields((2, 6, 32, 64), 191)
+    xb, pb = fields((2, 5, 64, 256), 192)
+    fused = Plan(6, 32, 64, 2, parity=pa, L=np.array([2.0, 0.7]))
+    assert fused.get_fused()[1] > 0
+    plain = Plan(5, 64, 256, 2, parity=pb, L=np.array([2.0, 0.7]))
+
+    def calls(a, b):
+        fused.apply(a, out=a)
+        plain.apply(b, out=b)
+        fused.apply_adjoint(a, out=a)
+        plain.apply_adjoint(b, out=b)
+
+    ea, eb = torch.from_numpy(xa).cuda(), torch.from_numpy(xb).cuda()
+    calls(ea, eb)
+    torch.cuda.synchronize()
+    a, b = torch.from_numpy(xa).cuda(), torch.from_numpy(xb).cuda()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        calls(a, b)                                  # warm-up before the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        calls(a, b)
+    sa, sb = torch.from_numpy(xa).cuda(), torch.from_numpy(xb).cuda()
+    for k in range(4):
+        a.copy_(sa)
+        b.copy_(sb)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(a, ea) and torch.equal(b, eb), k
+        _ = (sa * 2.0).sum().item()                   # eager work between replays
+    fused.close()
+    plain.close()
